@@ -1,0 +1,190 @@
+#!/usr/bin/env python
+"""Throughput of the differentiable edge-sampling path tracer on one MI355X.
+
+One step = drRender + drRenderBackward of the whole image: forward path
+tracing with checkpoints, primary edge samples, and the path backward pass
+(secondary edge samples at every vertex, interior adjoint, gradient scatter),
+including the per-view edge table and edge hierarchy builds.
+
+Workload (the benchmark metric's configuration): 512x512 pixels, 64 samples
+per pixel, path depth 3, a level-6 icosphere (81,920 triangles) displaced by
+seeded value noise inside a 12-triangle box lit by two quad lights (81,936
+triangles), gradients w.r.t. vertices, per-triangle albedo and camera.
+Inputs are seeded and synthetic and resident in HBM before timing starts.
+
+Prints one JSON line (see the field list at the bottom).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, public figure
+BVH_NODE_B = 64                 # bytes per BVH node fetch (two child boxes + links)
+TRI_B = 48                      # bytes per triangle fetch (v0, e1, e2 as 3 x float4)
+TREE_NODE_B = 168               # bytes per edge-tree node fetch (two children's bounds + links)
+ATOMIC_B = 8                    # read + write of one FP32 gradient entry
+BWD_UNIT_B = 2 * (4 + 12) + 1 + 4 + 4   # checkpoint reads (2 vertices), NEE bits, d_image, unit mask/ids
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1904_12228_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM bytes per backward launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE), if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_backward_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, threads):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload:
+    a 512x128-pixel band at the full 64 spp and depth 3, forward + backward."""
+    import numpy as np
+
+    import oracle
+    cam = cfg.camera.with_window(0, 192, 512, 320)
+    x0, y0, x1, y1 = cam.win()
+    dimg = np.random.default_rng(1).normal(size=(y1 - y0, x1 - x0)) + 0.5
+    units = (x1 - x0) * (y1 - y0) * cfg.spp
+    t0 = time.perf_counter()
+    oracle.render(cfg.scene, cam, cfg.spp, cfg.max_depth, 0, d_image=dimg, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": units / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{x1 - x0}x{y1 - y0} pixel window of the 512x512 image at {cfg.spp} spp, depth "
+                      f"{cfg.max_depth}: {units} fwd+bwd pixel samples in {dt:.1f} s (FP64, {threads} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the gradient all-reduce across GPUs is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1904_12228_amd import api, scenegen
+
+    cfg = scenegen.CONFIGS[args.workload]()
+    cam = cfg.camera
+    W, H, spp, depth = cam.width, cam.height, cfg.spp, cfg.max_depth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S = api.Scene(cfg.scene, device=dev)
+    d_image = torch.as_tensor(np.random.default_rng(0).normal(size=(H, W)) + 0.5, dtype=torch.float32, device=dev)
+    img = torch.empty((H, W), dtype=torch.float32, device=dev)
+    dv = torch.empty((S.num_vertices, 3), dtype=torch.float32, device=dev)
+    da = torch.empty((S.num_triangles,), dtype=torch.float32, device=dev)
+    dc = torch.empty((9,), dtype=torch.float32, device=dev)
+
+    def step(i):
+        S.render(cam, spp, depth, seed=i, out=img)
+        S.render_backward(cam, spp, depth, d_image, seed=i, outs=(dv, da, dc))
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    print(f"warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    # work counts per kernel launch (outside the timed region)
+    S.set_profiling(events=False, counters=True)
+    step(999)
+    counts = S.profile(reset=True)["counts"]
+    print("counting pass done", file=sys.stderr, flush=True)
+
+    # timed region: per-kernel HIP events on the library's stream
+    S.set_profiling(events=True, counters=False)
+    S.profile(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = S.profile(reset=True)
+    assert not S.device_error(), "device-side error flag set"
+    assert torch.isfinite(img).all() and torch.isfinite(dv).all(), "non-finite output"
+    print("timed steps done", file=sys.stderr, flush=True)
+
+    ms = (t1 - t0) * 1e3 / args.steps
+    samples = W * H * spp
+    value = samples / (ms * 1e-3)
+    units = W * H * spp
+    bw = counts["backward"]
+    bwd_bytes = (bw["bvh_nodes"] * BVH_NODE_B + bw["bvh_tris"] * TRI_B + bw["tree_nodes"] * TREE_NODE_B
+                 + bw["atomics"] * ATOMIC_B + units * BWD_UNIT_B)
+    bwd_ms = prof["backward_ms"] / max(prof["backward_launches"], 1)
+    achieved = bwd_bytes / (bwd_ms * 1e-3) / 1e9
+    kernels = {
+        "forward_ms": prof["forward_ms"] / max(prof["forward_launches"], 1),
+        "primary_ms": prof["primary_ms"] / max(prof["primary_launches"], 1),
+        "backward_ms": bwd_ms,
+        "other_ms": ms - (prof["forward_ms"] + prof["primary_ms"] + prof["backward_ms"]) / args.steps,
+        "counts_per_step": counts,
+    }
+    out = {
+        "metric": "fwd+bwd samples/s at 512^2 64spp",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded scene generator)",
+        "config": {"workload": f"{args.workload}: {W}x{H}, {spp} spp, depth {depth}, "
+                               f"{S.num_triangles} triangles, {S.num_edges} edges",
+                   "width": W, "height": H, "spp": spp, "max_depth": depth,
+                   "triangles": S.num_triangles, "edges": S.num_edges},
+        "roofline": {"bound": "hbm", "kernel": "k_backward (paths: secondary edges + interior adjoint + scatter)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": read_traffic(args.workload),
+                     "algorithmic_bytes_per_launch": bwd_bytes},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print("running the CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_threads)
+    S.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

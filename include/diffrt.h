@@ -1,0 +1,149 @@
+/*
+ * diffrt: differentiable Monte Carlo path tracer with edge sampling for
+ * AMD Instinct MI355X (gfx950). C ABI.
+ *
+ * The operation (Li, "Differentiable Visual Computing", Ch. 5, Method): given
+ * a triangle scene with continuous parameters Phi (vertex positions, per-
+ * triangle albedo, camera pose), render an image by Monte Carlo path tracing
+ * (eq. first, eq. gradient_monte_carlo, box pixel filter) and, given the
+ * gradient of a scalar loss w.r.t. that image, return the loss gradient w.r.t.
+ * Phi. The gradient is split by the product rule (eq. redner_product_rule)
+ * into an interior term (reverse mode through each path sample with its
+ * integration variables held fixed) and boundary terms sampled on silhouette
+ * edges: on screen (eq. edge_equation, eq. mc) and from every path vertex in
+ * direction space (Secondary visibility, eq. dirac_3d_edge), the latter drawn
+ * from a per-view edge hierarchy (Importance Sampling the Edges).
+ *
+ * Conventions
+ *  - Every array pointer is DEVICE memory owned by the caller, who keeps it
+ *    alive until the work queued on `stream` has completed. The library owns
+ *    the scene internals (BVH, edge tables, edge hierarchy, checkpoints) and
+ *    frees them in drSceneDestroy.
+ *  - Outputs are overwritten, not accumulated. A NULL gradient pointer skips
+ *    that output.
+ *  - All calls are asynchronous on `stream` unless stated; host-side argument
+ *    checks fail fast with DR_ERROR_INVALID_VALUE before anything is queued.
+ *    Device-side anomalies (traversal stack or tree-depth overflow) set a
+ *    sticky flag read by drGetLastDeviceError.
+ *  - A scene is not thread-safe; calls on one scene must be ordered.
+ *  - drRenderBackward differentiates the estimator drawn by drRender with the
+ *    same camera and options (seed, spp, depth): it reuses the forward pass's
+ *    path checkpoints when they match and recomputes them otherwise.
+ */
+#ifndef DIFFRT_H
+#define DIFFRT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DR_SUCCESS = 0,
+    DR_ERROR_INVALID_VALUE = 1,   /* bad pointer, size, index or option */
+    DR_ERROR_OUT_OF_MEMORY = 2,   /* device allocation failed */
+    DR_ERROR_DEVICE = 3,          /* a HIP call failed, or a sticky device error is set */
+    DR_ERROR_UNSUPPORTED = 4      /* e.g. an edge shared by more than two triangles */
+} drStatus;
+
+typedef struct drScene_t* drScene;
+
+/* Scene description (thesis Ch. 5, Method: triangle meshes, no
+ * interpenetration, area lights only). Arrays are device memory, read during
+ * drSceneCreate only (the library copies what it needs). */
+typedef struct {
+    int32_t num_vertices;        /* V >= 3 */
+    int32_t num_triangles;       /* T >= 1 */
+    const float*   vertices;     /* [V][3] world-space positions */
+    const int32_t* indices;      /* [T][3] vertex indices, 0 <= i < V */
+    const float*   normals;      /* [V][3] shading normals, or NULL for flat shading */
+    const float*   albedo;       /* [T] Lambertian albedo (emitters: 0) */
+    const float*   emission;     /* [T] radiance of emitters (> 0), 0 otherwise */
+    int32_t emission_two_sided;  /* 0: emitters radiate along (v1-v0)x(v2-v0) only */
+    float   background;          /* radiance of camera rays that hit nothing */
+} drSceneDesc;
+
+/* Pinhole look-at camera. Screen coordinates are pixels, y down; the ray
+ * through screen point (x, y) has direction f + ndc_x*aspect*tan(fov/2)*r +
+ * ndc_y*tan(fov/2)*u, so its parameter is camera-space depth. Geometry closer
+ * than near_clip is invisible and edges are clipped there. `window` selects
+ * the rendered pixels [x0,x1) x [y0,y1) of the full width x height image;
+ * images passed to the calls below have the window's size. */
+typedef struct {
+    float position[3], look_at[3], up[3];
+    float fov_y_deg;
+    float near_clip;
+    int32_t width, height;
+    int32_t window[4];           /* x0, y0, x1, y1; all zero = full image */
+} drCamera;
+
+/* Terms of the gradient (all on by default; switches exist for tests). */
+#define DR_TERM_INTERIOR  1u
+#define DR_TERM_PRIMARY   2u
+#define DR_TERM_SECONDARY 4u
+#define DR_TERM_ALL       7u
+
+typedef struct {
+    int32_t  spp;                /* samples per pixel, >= 1 */
+    int32_t  max_depth;          /* 0 = primary visibility (emission only); k = k path vertices with NEE; <= 6 */
+    uint64_t seed;               /* Philox4x32-10 key */
+    uint32_t view_id;            /* Philox counter word distinguishing views */
+    uint32_t terms;              /* DR_TERM_* bits; 0 means DR_TERM_ALL */
+    const uint8_t* unit_mask;    /* [M] device, or NULL. M = window pixels * spp; unit m
+                                    = pixel sample m plus primary edge sample m; 0 = skip */
+} drRenderOptions;
+
+/* Creates a scene: validates sizes and indices (host copy of the topology),
+ * extracts unique edges (sorted by (min vertex, max vertex)), builds the
+ * triangle BVH. Synchronises `stream`. */
+drStatus drSceneCreate(drScene* out, const drSceneDesc* desc, hipStream_t stream);
+
+/* Replaces all vertex positions ([V][3] device) and rebuilds the BVH. */
+drStatus drSceneUpdateVertices(drScene scene, const float* vertices, hipStream_t stream);
+
+/* Host query of the scene's sizes. */
+drStatus drSceneGetInfo(drScene scene, int32_t* num_vertices, int32_t* num_triangles, int32_t* num_edges);
+
+/* Forward pass: image[Hw][Ww] (window size), mean radiance per pixel. Stores
+ * the path checkpoints drRenderBackward reuses. */
+drStatus drRender(drScene scene, const drCamera* camera, const drRenderOptions* options,
+                  float* image, hipStream_t stream);
+
+/* Backward pass for the loss gradient d_image[Hw][Ww]: writes
+ * d_vertices[V][3], d_albedo[T], d_camera[9] (position, look_at, up). */
+drStatus drRenderBackward(drScene scene, const drCamera* camera, const drRenderOptions* options,
+                          const float* d_image, float* d_vertices, float* d_albedo, float* d_camera,
+                          hipStream_t stream);
+
+/* Measurement support (not needed for rendering). With `events` on, every
+ * forward, primary-edge and path-backward kernel launch is bracketed by HIP
+ * events on the stream it runs on; with `counters` on, the kernels also count
+ * their memory work (BVH node and triangle fetches, edge-tree node fetches,
+ * gradient atomics, rays). Counting adds an atomic per lane and launch. */
+typedef struct {
+    double forward_ms, primary_ms, backward_ms;              /* summed kernel durations */
+    int64_t forward_launches, primary_launches, backward_launches;
+    /* per kernel (0 forward, 1 primary edges, 2 path backward): BVH node
+     * fetches, triangle fetches, edge-tree node fetches, gradient atomics, rays */
+    int64_t counts[3][5];
+} drProfile;
+
+drStatus drSetProfiling(drScene scene, int32_t events, int32_t counters);
+
+/* Synchronises, returns the sums since the last reset, and optionally resets. */
+drStatus drGetProfile(drScene scene, drProfile* out, int32_t reset);
+
+/* Synchronises the scene's last stream and returns DR_ERROR_DEVICE if a
+ * device-side anomaly was recorded (then clears it). */
+drStatus drGetLastDeviceError(drScene scene);
+
+drStatus drSceneDestroy(drScene scene);
+
+const char* drGetErrorString(drStatus status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_map>
 #include <vector>
@@ -37,7 +39,7 @@ const double kPi = 3.14159265358979323846;
 // is flagged when one of its discrete decisions lies this close to a tie, so
 // that an FP32 implementation may legitimately decide the other way.
 // ---------------------------------------------------------------------------
-const double kTieBary = 1e-5;     // barycentric distance to a triangle edge
+const double kTieWorld = 5e-7;    // ray-to-triangle-edge distance, relative to the scene diagonal
 const double kTieT = 1e-6;        // relative distance between hit distances
 const double kTieCos = 1e-5;      // |cos| of grazing hits
 const double kTieU = 1e-5;        // uniform vs. branch probability
@@ -53,6 +55,7 @@ const double kEps3 = 1e-4;        // secondary: angular offset of the two sides
 const double kTminRel = 1e-4;     // secondary ray t_min, relative to scene diagonal
 const double kShadowEnd = 1e-4;   // shadow rays stop at (1 - this) * distance
 const double kInsidePad = 1e-4;   // "point inside the parent box" uses the box grown by this * diagonal
+const double kVsphereMargin = 1e-5;  // v-sphere pruning only beyond this relative margin (conservative)
 const double kHorizon = 1e-5;     // edge points within this * diagonal of the tangent plane are skipped
 
 // Philox counter tags.
@@ -184,6 +187,7 @@ struct Scn {
     double atot = 0;
     std::vector<BNode> bvh;
     std::vector<int> border;
+    std::vector<double> tie_bary;   // per triangle: near-edge threshold in barycentric units
     bool use_bvh = true;
 
     V3d p(int v) const { return {P[3 * v], P[3 * v + 1], P[3 * v + 2]}; }
@@ -308,6 +312,12 @@ int prepare(const orc_scene* d, Scn& s) {
             s.lcdf.push_back(s.atot);
         }
     for (double& c : s.lcdf) c /= s.atot;
+    s.tie_bary.resize(s.T);
+    for (int f = 0; f < s.T; ++f) {
+        V3d a = s.p(s.I[3 * f]), b = s.p(s.I[3 * f + 1]), c = s.p(s.I[3 * f + 2]);
+        double e = std::min(length(b - a), std::min(length(c - b), length(a - c)));
+        s.tie_bary[f] = kTieWorld * s.diag / e;
+    }
     build_bvh(s);
     return ORC_OK;
 }
@@ -370,7 +380,7 @@ void for_candidates(const Scn& s, const V3d& o, const V3d& d, double tmin, doubl
         for (int f = 0; f < s.T; ++f) fn(f);
         return;
     }
-    double pad = kTieBary * s.diag + 1e-12;
+    double pad = kTieWorld * s.diag + 1e-12;
     double dl = length(d);
     std::vector<int> st{0};
     while (!st.empty()) {
@@ -398,7 +408,7 @@ Hit closest(const Scn& s, const V3d& o, const V3d& d, double tmin, double tmax, 
         TriHit h = tri_test(s, f, o, d, tmin, tmax);
         if (!h.valid) return;
         if (h.ok && (h.t < best.t || (h.t == best.t && f < best.tri))) best = {f, h.t, h.u, h.v};
-        bool near_edge = std::fabs(h.m) < kTieBary;
+        bool near_edge = std::fabs(h.m) < s.tie_bary[f];
         bool in_range = h.t > tmin * (1 - kTieT) - 1e-300 && h.t < tmax * (1 + kTieT);
         if ((near_edge && in_range) || h.ok) nears.push_back({f, h.t, h.ok});
     });
@@ -412,7 +422,7 @@ Hit closest(const Scn& s, const V3d& o, const V3d& d, double tmin, double tmax, 
     }
     if (best.tri >= 0) {
         double m = std::min(std::min(best.u, best.v), 1 - best.u - best.v);
-        if (m < kTieBary) TIE(U, 2);
+        if (m < s.tie_bary[best.tri]) TIE(U, 2);
         if (std::fabs(best.t - tmin) <= kTieT * std::max(best.t, tmin)) TIE(U, 3);
         V3d n = normalize(s.face_n(best.tri));
         if (std::fabs(dot(n, normalize(d))) < kTieCos) TIE(U, 4);
@@ -429,8 +439,8 @@ bool occluded(const Scn& s, const V3d& o, const V3d& d, double tmin, double tmax
         if (!h.valid) return;
         if (h.ok) any = true;
         bool in_range = h.t > tmin * (1 - kTieT) && h.t < tmax * (1 + kTieT);
-        if (in_range && std::fabs(h.m) < kTieBary) TIE(U, 5);
-        if (h.ok || std::fabs(h.m) < kTieBary) {
+        if (in_range && std::fabs(h.m) < s.tie_bary[f]) TIE(U, 5);
+        if (h.ok || std::fabs(h.m) < s.tie_bary[f]) {
             if (std::fabs(h.t - tmin) <= kTieT * std::max(h.t, tmin) || std::fabs(h.t - tmax) <= kTieT * tmax)
                 TIE(U, 6);
         }
@@ -497,7 +507,7 @@ bool disc_from(const Scn& s, const Edge& e, const V3d& q, bool* tie) {
 // clip, screen length, FP64 CDF (Primary Visibility; edge chosen with
 // probability proportional to clipped screen length, point uniform on it).
 // ---------------------------------------------------------------------------
-struct PEdge { double A[2], B[2], Ac[2], Bc[2], len; };
+struct PEdge { double A[2], B[2], Ac[2], Bc[2], Aa[2], Ba[2], len; };  // Aa, Ba: alpha points
 
 struct View {
     Cam<double> cam;
@@ -525,7 +535,8 @@ bool clip_segment(double A[2], double B[2], double x0, double y0, double x1, dou
     return true;
 }
 
-// Near-clipped endpoints of an edge (camera-space depth >= near).
+// Near-clipped endpoints of an edge (camera-space depth >= near): the part of
+// the edge that can be sampled on screen.
 template <class S> bool near_clip(const Cam<S>& k, V3<S> a, V3<S> b, V3<S>& ao, V3<S>& bo) {
     S za = dot(a - k.c, k.f), zb = dot(b - k.c, k.f);
     if (val(za) < k.near && val(zb) < k.near) return false;
@@ -533,6 +544,26 @@ template <class S> bool near_clip(const Cam<S>& k, V3<S> a, V3<S> b, V3<S>& ao, 
     if (val(za) < k.near) ao = a + (b - a) * ((k.near - za) / (zb - za));
     if (val(zb) < k.near) bo = b + (a - b) * ((k.near - zb) / (za - zb));
     return true;
+}
+
+// Two points of the edge whose projections define the edge equation alpha
+// (eq. edge_equation). The projected line, and hence the boundary term
+// d alpha/d Phi / |grad_xy alpha|, is the same for any two points of the edge
+// in front of the camera; an endpoint behind the near plane is replaced by the
+// edge point at depth max(near, half the other endpoint's depth), which keeps
+// the projection well conditioned (a point at depth `near` projects far off
+// screen with a 1/near^2 Jacobian).
+template <class S> void alpha_points(const Cam<S>& k, V3<S> a, V3<S> b, V3<S>& ao, V3<S>& bo) {
+    S za = dot(a - k.c, k.f), zb = dot(b - k.c, k.f);
+    ao = a; bo = b;
+    if (val(za) < k.near) {
+        S zd = val(zb) * 0.5 > k.near ? zb * 0.5 : cst<S>(k.near);
+        ao = a + (b - a) * ((zd - za) / (zb - za));
+    }
+    if (val(zb) < k.near) {
+        S zd = val(za) * 0.5 > k.near ? za * 0.5 : cst<S>(k.near);
+        bo = b + (a - b) * ((zd - zb) / (za - zb));
+    }
 }
 
 double cam_param(const orc_camera& oc, int k) {
@@ -561,6 +592,10 @@ void build_view(const Scn& s, const orc_camera& oc, View& vw) {
                 project(vw.cam, b, p.B[0], p.B[1]);
                 if (clip_segment(p.A, p.B, vw.x0, vw.y0, vw.x1, vw.y1, p.Ac, p.Bc))
                     p.len = std::hypot(p.Bc[0] - p.Ac[0], p.Bc[1] - p.Ac[1]);
+                V3d aa, ba;
+                alpha_points(vw.cam, s.p(e.va), s.p(e.vb), aa, ba);
+                project(vw.cam, aa, p.Aa[0], p.Aa[1]);
+                project(vw.cam, ba, p.Ba[0], p.Ba[1]);
             }
         }
         acc += p.len;
@@ -765,9 +800,10 @@ bool vsphere_prune(const ENode& n, const V3d& pc /* p - camera */, Unit* U) {
             double fa = std::max(std::fabs(lo - sv[k]), std::fabs(hi - sv[k]));
             far2 += fa * fa;
         }
-        out[f] = d2 > r2;
-        in[f] = far2 < r2;
-        if (U && (std::fabs(d2 - r2) < kTieBox * r2 || std::fabs(far2 - r2) < kTieBox * r2)) TIE(*U, 10);
+        double ro = r2 * (1 + kVsphereMargin), ri = r2 * (1 - kVsphereMargin);
+        out[f] = d2 > ro;
+        in[f] = far2 < ri;
+        if (U && (std::fabs(d2 - ro) < kTieBox * r2 || std::fabs(far2 - ri) < kTieBox * r2)) TIE(*U, 10);
     }
     return (out[0] && out[1]) || (in[0] && in[1]);
 }
@@ -810,7 +846,7 @@ void root_box(const ETree& t, double lo[3], double hi[3]) {
 
 // Single descent with one uniform per level. Returns the edge or -1.
 template <class LevelU>
-int tree_sample(const TreeQuery& q, double u_root, LevelU&& ulev, double& pdf, Unit* U) {
+int tree_sample(const TreeQuery& q, double u_root, LevelU&& ulev, double& pdf, Unit* U, bool dbg = false) {
     const ETree& t = *q.t;
     double lo[3], hi[3];
     root_box(t, lo, hi);
@@ -833,6 +869,7 @@ int tree_sample(const TreeQuery& q, double u_root, LevelU&& ulev, double& pdf, U
         double pl = wl / (wl + wr);
         double u = ulev(level);
         if (U && std::fabs(u - pl) < kTieU) TIE(*U, 11);
+        if (dbg) std::fprintf(stderr, "  level %d w0 %.9g w1 %.9g u %.9g side %d\n", level, wl, wr, u, u < pl ? 0 : 1);
         if (u < pl) { pdf *= pl; node = n.left; }
         else { pdf *= wr / (wl + wr); node = n.right; }
         ++level;
@@ -891,7 +928,33 @@ template <class S> struct PathVtx {
     V3<S> x, ns;
     S rho, beta;
     int tri;
+    double dx;      // first-order FP32 position error bound of x, in units of u32 (absolute)
+    double kappa;   // relative sensitivity of this vertex's contributions, in units of u32
 };
+
+// First-order rounding-error model of an FP32 evaluation of the same path
+// (used only to scale the parity tolerance): positions carry an absolute
+// error dx, directions a relative error dw (both in units of u32). A hit at
+// distance t inherits dx + t*dw; the barycentric coordinates of a hit on a
+// triangle with shortest edge e are then off by dx/e, which moves an
+// interpolated normal by dx*g (g = normal variation / e) and the next sampled
+// direction with it.
+struct Cond {
+    double dx = 0, dw = 4, kmax = 0;   // kmax: accumulated sensitivity along the path
+};
+const double kOpsU32 = 650;   // FP32 operations budget of one contribution (tolerance floor)
+const double kCondSafety = 8; // the first-order model above underestimates compounded sensitivities
+
+double min_edge(const Scn& s, int f) {
+    V3d a = s.p(s.I[3 * f]), b = s.p(s.I[3 * f + 1]), c = s.p(s.I[3 * f + 2]);
+    return std::min(length(b - a), std::min(length(c - b), length(a - c)));
+}
+
+double normal_spread(const Scn& s, int f) {
+    if (!s.smooth) return 0;
+    V3d n0 = s.nrm(s.I[3 * f]), n1 = s.nrm(s.I[3 * f + 1]), n2 = s.nrm(s.I[3 * f + 2]);
+    return std::max(length(n1 - n0), std::max(length(n2 - n1), length(n0 - n2)));
+}
 
 // Ray-plane intersection of a ray with the plane of a triangle; moves with the
 // ray origin, its direction and the triangle vertices.
@@ -971,7 +1034,7 @@ V3d cosine_dir(const V3d& n, double u0, double u1) {
 // camera = true: t_min = near clip, misses return the background radiance.
 template <class S>
 S radiance_impl(const Env<S>& E, Unit& U, const Stream& rs, int base, const V3<S>& o, const V3<S>& d0, double tmin,
-                bool camera, int budget, std::vector<PathVtx<S>>* log) {
+                bool camera, int budget, std::vector<PathVtx<S>>* log, Cond* cond = nullptr) {
     const Scn& s = *E.s;
     V3d dv = valv(d0);
     Hit h = closest(s, valv(o), dv, tmin, 1e300, U);
@@ -982,12 +1045,28 @@ S radiance_impl(const Env<S>& E, Unit& U, const Stream& rs, int base, const V3<S
     bool front = dot(dv, s.face_n(tri)) < 0;
     S L = cst<S>(emitted(s, tri, front));
     S beta = cst<S>(1.0);
+    double seg = h.t * length(dv);
     for (int k = 1; k <= budget; ++k) {
         V3<S> ns = shading_normal(s, tri, x, p0, p1, p2);
         if (!front) ns = -ns;
         S rho = E.albedo(tri);
         if (val(rho) == 0) break;
-        if (log) log->push_back(PathVtx<S>{x, ns, rho, beta, tri});
+        double kap = 0, dxv = 0;
+        if (cond) {
+            // incidence cosine: errors across the ray are stretched by 1/c on the
+            // surface, and the ray-plane adjoint carries t/(d.n)
+            double c = std::max(std::fabs(dot(normalize(dv), normalize(s.face_n(tri)))), 1e-6);
+            cond->dx = (cond->dx + seg * cond->dw) / c + 4 * length(valv(x));
+            double e = min_edge(s, tri);
+            double dn = 4 + cond->dx * normal_spread(s, tri) / e;
+            // adjoints flowing back to earlier vertices pass through every
+            // ray-plane intersection on the way: sensitivities add up
+            kap = cond->kmax + 4 + cond->dx / e + dn + cond->dw / c;
+            cond->kmax = kap;
+            cond->dw = 8 + dn;
+            dxv = cond->dx;
+        }
+        if (log) log->push_back(PathVtx<S>{x, ns, rho, beta, tri, dxv, kap});
         double* dl = (log && U.dir_mode && k <= 6) ? U.dir + 10 * (k - 1) : nullptr;
         L = L + beta * nee(E, U, rs, base + 2 * k - 1, x, ns, rho, dl);
         if (k == budget) break;
@@ -1003,10 +1082,12 @@ S radiance_impl(const Env<S>& E, Unit& U, const Stream& rs, int base, const V3<S
         if (h2.tri < 0) break;
         // Continuation weight f*cos/pdf with the pdf held constant.
         beta = beta * (rho * dot(ns, lift<S>(w)) / cv);
+        seg = h2.t;
         tri = h2.tri;
         p0 = E.P(s.I[3 * tri]); p1 = E.P(s.I[3 * tri + 1]); p2 = E.P(s.I[3 * tri + 2]);
         x = ray_plane(x, lift<S>(w), p0, p1, p2);
         front = dot(w, s.face_n(tri)) < 0;
+        dv = w;
     }
     return L;
 }
@@ -1051,9 +1132,18 @@ void sweep(const Ctx& C, const Leaves& L, int32_t out, double seed, std::vector<
         if (L.cam[k] <= out && adj[L.cam[k]] != 0) res.push_back({3 * C.V + C.T + k, adj[L.cam[k]]});
 }
 
+int debug_unit() {
+    static int u = [] {
+        const char* e = std::getenv("ORC_DEBUG_UNIT");
+        return e ? std::atoi(e) : -1;
+    }();
+    return u;
+}
+
 void run_unit(const Ctx& C, int m, Acc& acc) {
     const Scn& s = *C.s;
     const orc_options& o = *C.o;
+    const bool dbg = m == debug_unit();
     if (o.unit_mask && !o.unit_mask[m]) return;
     TP.clear();
     Leaves L;
@@ -1078,15 +1168,21 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
     Env<double> Ev{&s};
     std::vector<PathVtx<D>> verts;
     V3<D> dir = cam_dir(cam, sx, sy);
-    D Lr = radiance_impl<D>(Ed, U, rc, 0, cam.c, dir, C.oc->near_clip, true, o.max_depth, &verts);
+    Cond cmain;
+    cmain.dx = 4 * length(valv(cam.c));
+    D Lr = radiance_impl<D>(Ed, U, rc, 0, cam.c, dir, C.oc->near_clip, true, o.max_depth, &verts, &cmain);
     std::vector<std::pair<int, double>> contrib;
     std::vector<double> sweep_mass_keys;
     std::vector<std::vector<std::pair<int, double>>> parts;
+    // Rounding scale of each part: a boundary sample's weight is a difference
+    // of two radiances, whose rounding error scales with |a| + |b|.
+    std::vector<double> scales;
     int64_t used_p = 0, used_s = 0;
     if (C.d_image) {
         double wimg = C.d_image[pix] / C.spp;
         if (o.interior) {
             parts.emplace_back();
+            scales.push_back(1.0 + kCondSafety * cmain.kmax / kOpsU32);
             sweep(C, L, Lr.i, wimg, parts.back());
         }
         // Secondary boundary term at every path vertex (one edge sample each).
@@ -1106,7 +1202,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                     int blk = 1 + lev / 4;
                     if (blk != cached) { rk.block((uint32_t)blk, cache); cached = blk; }
                     return cache[lev % 4];
-                }, pdf, &U);
+                }, pdf, &U, dbg);
                 if (ei < 0) continue;
                 const Edge& e = s.edges[ei];
                 if (e.f0 == pv.tri || e.f1 == pv.tri) continue;
@@ -1125,17 +1221,30 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 V3d wh = w / wl;
                 V3d wp = normalize(wh + nh * kEps3), wm = normalize(wh - nh * kEps3);
                 int rem = o.max_depth - k;
-                double Lp = radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wp, s.tmin, false, rem, nullptr);
-                double Lm = radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wm, s.tmin, false, rem, nullptr);
-                double Fp = val(pv.rho) / kPi * std::max(0.0, dot(nsv, wp)) * Lp;
-                double Fm = val(pv.rho) / kPi * std::max(0.0, dot(nsv, wm)) * Lm;
+                Cond cp, cm;
+                cp.dx = cm.dx = pv.dx;
+                cp.dw = cm.dw = 8 + pv.dx / wl;
+                cp.kmax = cm.kmax = pv.kappa;
+                double Lp = radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wp, s.tmin, false, rem, nullptr, &cp);
+                double Lm = radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wm, s.tmin, false, rem, nullptr, &cm);
+                double kap_s = std::max(pv.kappa, std::max(cp.kmax, cm.kmax)) + pv.dx / wl;
+                // The cosine factor is continuous across the edge: both one-sided
+                // limits share the cosine at the edge point; only L jumps.
+                double cosw = dot(nsv, wh);
+                double Fp = val(pv.rho) / kPi * cosw * Lp;
+                double Fm = val(pv.rho) / kPi * cosw * Lm;
                 used_s++;
                 if (Fp == Fm) continue;
                 double W = C.d_image[pix] * val(pv.beta) / C.spp;
                 double wgt = W * (Fp - Fm) * length(cross(pb - pa, wh)) / (cn * wl * pdf);
+                if (dbg)
+                    std::fprintf(stderr, "unit %d vertex %d tri %d p=(%.9g %.9g %.9g) n=(%.9g %.9g %.9g) edge %d pdf %.9g "
+                                 "t %.9g Lp %.9g Lm %.9g cos %.9g W %.9g wgt %.9g kappa %.3g\n",
+                                 m, k, pv.tri, p.x, p.y, p.z, nsv.x, nsv.y, nsv.z, ei, pdf, b0[1], Lp, Lm, cosw, W, wgt, kap_s);
                 V3<D> A = Ed.P(e.va), B = Ed.P(e.vb);
                 D beta = dot(lift<D>(wh), cross(A - pv.x, B - pv.x));
                 parts.emplace_back();
+                scales.push_back((1.0 + kCondSafety * kap_s / kOpsU32) * (std::fabs(Fp) + std::fabs(Fm)) / std::fabs(Fp - Fm));
                 sweep(C, L, beta.i, wgt, parts.back());
             }
         }
@@ -1149,13 +1258,29 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             const PEdge& pe = vw.pe[ei];
             double t = b0[1];
             double x = pe.Ac[0] + (pe.Bc[0] - pe.Ac[0]) * t, y = pe.Ac[1] + (pe.Bc[1] - pe.Ac[1]) * t;
-            double nl = std::hypot(pe.A[0] - pe.B[0], pe.A[1] - pe.B[1]);
-            double nx = (pe.A[1] - pe.B[1]) / nl, ny = (pe.B[0] - pe.A[0]) / nl;
+            double nl = std::hypot(pe.Aa[0] - pe.Ba[0], pe.Aa[1] - pe.Ba[1]);
+            double nx = (pe.Aa[1] - pe.Ba[1]) / nl, ny = (pe.Ba[0] - pe.Aa[0]) / nl;
             V3d cpos = vw.cam.c;
+            Cond cu, cl;
+            cu.dx = cl.dx = 4 * length(cpos);
             double fu = radiance_impl<double>(Ev, U, rp, 0, cpos, cam_dir(vw.cam, x + kEpsPx * nx, y + kEpsPx * ny),
-                                              C.oc->near_clip, true, o.max_depth, nullptr);
+                                              C.oc->near_clip, true, o.max_depth, nullptr, &cu);
             double fl = radiance_impl<double>(Ev, U, rp, 0, cpos, cam_dir(vw.cam, x - kEpsPx * nx, y - kEpsPx * ny),
-                                              C.oc->near_clip, true, o.max_depth, nullptr);
+                                              C.oc->near_clip, true, o.max_depth, nullptr, &cl);
+            double kap_p = std::max(cu.kmax, cl.kmax);
+            {
+                // a near-clipped endpoint sits at depth `near`: its projection and
+                // the clip parameter amplify FP32 position errors by ~distance/near
+                const Edge& ce = s.edges[ei];
+                V3d pa = s.p(ce.va), pb = s.p(ce.vb);
+                double za = dot(pa - vw.cam.c, vw.cam.f), zb = dot(pb - vw.cam.c, vw.cam.f);
+                if (za < vw.cam.near || zb < vw.cam.near)
+                    kap_p += 4 * (length(pa - vw.cam.c) + length(pb - vw.cam.c)) /
+                             std::max(vw.cam.near, 0.5 * std::max(za, zb));
+            }
+            if (dbg)
+                std::fprintf(stderr, "punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g n %.9g %.9g fu %.9g fl %.9g total %.9g\n",
+                             m, ei, x, y, pe.Aa[0], pe.Aa[1], pe.Ba[0], pe.Ba[1], nx, ny, fu, fl, vw.psum);
             int ix = (int)std::floor(x), iy = (int)std::floor(y);
             ix = std::min(std::max(ix, vw.x0), vw.x1 - 1);
             iy = std::min(std::max(iy, vw.y0), vw.y1 - 1);
@@ -1168,12 +1293,13 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 double wgt = C.d_image[ppix] * (fu - fl) * vw.psum / ((double)C.M * nl);
                 const Edge& e = s.edges[ei];
                 V3<D> a3, b3;
-                near_clip(cam, Ed.P(e.va), Ed.P(e.vb), a3, b3);
+                alpha_points(cam, Ed.P(e.va), Ed.P(e.vb), a3, b3);
                 D ax, ay, bx, by;
                 project(cam, a3, ax, ay);
                 project(cam, b3, bx, by);
                 D alpha = (ay - by) * x + (bx - ax) * y + (ax * by - bx * ay);
                 parts.emplace_back();
+                scales.push_back((1.0 + kCondSafety * kap_p / kOpsU32) * (std::fabs(fu) + std::fabs(fl)) / std::fabs(fu - fl));
                 sweep(C, L, alpha.i, wgt, parts.back());
             }
         }
@@ -1186,10 +1312,10 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
     acc.pedge += used_p;
     acc.sedge += used_s;
     if (!acc.img.empty()) acc.img[pix] += Lr.v / C.spp;
-    for (const auto& part : parts)
-        for (const auto& pr : part) {
+    for (size_t i = 0; i < parts.size(); ++i)
+        for (const auto& pr : parts[i]) {
             acc.g[pr.first] += pr.second;
-            acc.mass[pr.first] += std::fabs(pr.second);
+            acc.mass[pr.first] += std::fabs(pr.second) * scales[i];
         }
 }
 

@@ -71,7 +71,8 @@ typedef struct {
     double* d_vertices;          /* [V][3] */
     double* d_albedo;            /* [T] */
     double* d_camera;            /* [9]: position, look_at, up */
-    double* mass_vertices;       /* [V][3] sum of |per-sample contribution|, or NULL */
+    double* mass_vertices;       /* [V][3] rounding scale: sum of |per-sample contribution| (boundary samples
+                                    scaled by (|f+| + |f-|) / |f+ - f-|), or NULL */
     double* mass_albedo;         /* [T] or NULL */
     double* mass_camera;         /* [9] or NULL */
     uint8_t* unit_flags;         /* [M] or NULL: 1 = a decision was within rounding of a tie */

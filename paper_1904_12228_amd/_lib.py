@@ -1,0 +1,91 @@
+"""ctypes declarations of the C ABI in include/diffrt.h (libdiffrt.so).
+
+Loading fails loudly when the library is missing: there is no fallback
+implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdiffrt.so")
+
+DR_SUCCESS = 0
+DR_TERM_INTERIOR = 1
+DR_TERM_PRIMARY = 2
+DR_TERM_SECONDARY = 4
+DR_TERM_ALL = 7
+
+# every entry point declared in include/diffrt.h
+EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneGetInfo", "drRender", "drRenderBackward",
+           "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy", "drGetErrorString"]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("num_vertices", C.c_int32), ("num_triangles", C.c_int32),
+                ("vertices", C.c_void_p), ("indices", C.c_void_p), ("normals", C.c_void_p),
+                ("albedo", C.c_void_p), ("emission", C.c_void_p),
+                ("emission_two_sided", C.c_int32), ("background", C.c_float)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("position", C.c_float * 3), ("look_at", C.c_float * 3), ("up", C.c_float * 3),
+                ("fov_y_deg", C.c_float), ("near_clip", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32), ("window", C.c_int32 * 4)]
+
+
+class RenderOptions(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
+                ("view_id", C.c_uint32), ("terms", C.c_uint32), ("unit_mask", C.c_void_p)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("forward_ms", C.c_double), ("primary_ms", C.c_double), ("backward_ms", C.c_double),
+                ("forward_launches", C.c_int64), ("primary_launches", C.c_int64),
+                ("backward_launches", C.c_int64), ("counts", (C.c_int64 * 5) * 3)]
+
+COUNT_NAMES = ["bvh_nodes", "bvh_tris", "tree_nodes", "atomics", "rays"]
+KERNELS = ["forward", "primary", "backward"]
+
+
+class DiffrtError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1904_12228_amd.build` "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32 = C.c_void_p, C.c_int32
+    sig = {
+        "drSceneCreate": [C.POINTER(vp), C.POINTER(SceneDesc), vp],
+        "drSceneUpdateVertices": [vp, vp, vp],
+        "drSceneGetInfo": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "drRender": [vp, C.POINTER(Camera), C.POINTER(RenderOptions), vp, vp],
+        "drRenderBackward": [vp, C.POINTER(Camera), C.POINTER(RenderOptions), vp, vp, vp, vp, vp],
+        "drSetProfiling": [vp, i32, i32],
+        "drGetProfile": [vp, C.POINTER(Profile), i32],
+        "drGetLastDeviceError": [vp],
+        "drSceneDestroy": [vp],
+        "drGetErrorString": [C.c_int],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_char_p if name == "drGetErrorString" else C.c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int, what: str):
+    if status != DR_SUCCESS:
+        msg = load().drGetErrorString(status).decode()
+        raise DiffrtError(f"{what} failed: {msg} ({status})")

@@ -1,0 +1,121 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+PyTorch provides device memory and the stream; every step of rendering and
+differentiation runs in the HIP kernels of libdiffrt.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev(a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        return a.detach().to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device).contiguous()
+
+
+def camera_struct(cam) -> _lib.Camera:
+    c = _lib.Camera()
+    c.position[:] = [float(v) for v in cam.position]
+    c.look_at[:] = [float(v) for v in cam.look_at]
+    c.up[:] = [float(v) for v in cam.up]
+    c.fov_y_deg = float(cam.fov_y_deg)
+    c.near_clip = float(cam.near_clip)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.window[:] = list(cam.win())
+    return c
+
+
+def options_struct(spp, max_depth, seed=0, view_id=0, terms=0, unit_mask=None) -> _lib.RenderOptions:
+    return _lib.RenderOptions(int(spp), int(max_depth), int(seed), int(view_id), int(terms), _ptr(unit_mask))
+
+
+class Scene:
+    """A scene uploaded to the GPU (owns the library's scene handle)."""
+
+    def __init__(self, scene, device="cuda"):
+        lib = _lib.load()
+        self.device = torch.device(device)
+        self.vertices = _dev(scene.vertices, torch.float32, self.device)
+        self.indices = _dev(scene.indices, torch.int32, self.device)
+        self.albedo = _dev(scene.albedo, torch.float32, self.device)
+        self.emission = _dev(scene.emission, torch.float32, self.device)
+        self.normals = None if scene.normals is None else _dev(scene.normals, torch.float32, self.device)
+        self.num_vertices = int(self.vertices.shape[0])
+        self.num_triangles = int(self.indices.shape[0])
+        desc = _lib.SceneDesc(self.num_vertices, self.num_triangles, _ptr(self.vertices), _ptr(self.indices),
+                              _ptr(self.normals), _ptr(self.albedo), _ptr(self.emission),
+                              int(bool(scene.emission_two_sided)), float(scene.background))
+        h = C.c_void_p()
+        _lib.check(lib.drSceneCreate(C.byref(h), C.byref(desc), _stream()), "drSceneCreate")
+        self._h = h
+        ne = C.c_int32()
+        lib.drSceneGetInfo(self._h, None, None, C.byref(ne))
+        self.num_edges = int(ne.value)
+
+    def update_vertices(self, vertices):
+        v = _dev(vertices, torch.float32, self.device)
+        assert v.shape == (self.num_vertices, 3)
+        self.vertices = v
+        _lib.check(_lib.load().drSceneUpdateVertices(self._h, _ptr(v), _stream()), "drSceneUpdateVertices")
+
+    def render(self, cam, spp, max_depth, seed=0, view_id=0, unit_mask=None, out=None):
+        x0, y0, x1, y1 = cam.win()
+        img = out if out is not None else torch.empty((y1 - y0, x1 - x0), dtype=torch.float32, device=self.device)
+        c = camera_struct(cam)
+        o = options_struct(spp, max_depth, seed, view_id, 0, unit_mask)
+        _lib.check(_lib.load().drRender(self._h, C.byref(c), C.byref(o), _ptr(img), _stream()), "drRender")
+        return img
+
+    def render_backward(self, cam, spp, max_depth, d_image, seed=0, view_id=0, terms=0, unit_mask=None,
+                        want=("vertices", "albedo", "camera"), outs=None):
+        d_image = _dev(d_image, torch.float32, self.device)
+        if outs is None:
+            dv = torch.empty((self.num_vertices, 3), dtype=torch.float32, device=self.device) if "vertices" in want else None
+            da = torch.empty((self.num_triangles,), dtype=torch.float32, device=self.device) if "albedo" in want else None
+            dc = torch.empty((9,), dtype=torch.float32, device=self.device) if "camera" in want else None
+        else:
+            dv, da, dc = outs
+        c = camera_struct(cam)
+        o = options_struct(spp, max_depth, seed, view_id, terms, unit_mask)
+        _lib.check(_lib.load().drRenderBackward(self._h, C.byref(c), C.byref(o), _ptr(d_image), _ptr(dv), _ptr(da),
+                                                _ptr(dc), _stream()), "drRenderBackward")
+        return dv, da, dc
+
+    def set_profiling(self, events=True, counters=False):
+        _lib.check(_lib.load().drSetProfiling(self._h, int(events), int(counters)), "drSetProfiling")
+
+    def profile(self, reset=True) -> dict:
+        p = _lib.Profile()
+        _lib.check(_lib.load().drGetProfile(self._h, C.byref(p), int(reset)), "drGetProfile")
+        out = {name: getattr(p, name) for name, _ in _lib.Profile._fields_ if name != "counts"}
+        out["counts"] = {k: {n: int(p.counts[i][j]) for j, n in enumerate(_lib.COUNT_NAMES)}
+                         for i, k in enumerate(_lib.KERNELS)}
+        return out
+
+    def device_error(self) -> bool:
+        return _lib.load().drGetLastDeviceError(self._h) != _lib.DR_SUCCESS
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().drSceneDestroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,336 @@
+// C ABI of the gfx950 differentiable path tracer (see include/diffrt.h).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "dr_host.h"
+
+using namespace dr;
+
+#define API_CHECK(x)                                       \
+    do {                                                   \
+        hipError_t e_ = (x);                               \
+        if (e_ != hipSuccess) return DR_ERROR_DEVICE;      \
+    } while (0)
+#define API_ALLOC(buf, n)                                                   \
+    do {                                                                    \
+        if ((buf).ensure(n) != hipSuccess) return DR_ERROR_OUT_OF_MEMORY;  \
+    } while (0)
+
+SceneView drScene_t::view() const {
+    SceneView v;
+    v.V = V; v.T = T; v.E = E; v.L = L;
+    v.P = P.as<float>();
+    v.I = I.as<int>();
+    v.N = smooth ? N.as<float>() : nullptr;
+    v.alb = alb.as<float>();
+    v.emi = emi.as<float>();
+    v.tri = tri.as<float4>();
+    v.bvh = bvh.as<BvhNode>();
+    v.edges = edges.as<int4>();
+    v.ekind = ekind.as<uint8_t>();
+    v.lights = lights.as<int>();
+    v.lcdf = lcdf.as<double>();
+    v.atot = atot;
+    v.diag = diag;
+    v.tmin = tmin;
+    v.two_sided = two_sided;
+    v.background = background;
+    v.err = err.as<int>();
+    return v;
+}
+
+static void release_all(drScene_t* s) {
+    Buf* bufs[] = {&s->P, &s->I, &s->N, &s->alb, &s->emi, &s->tri, &s->bvh, &s->edges, &s->ekind, &s->lights, &s->lcdf,
+                   &s->scal, &s->err, &s->codes, &s->ids, &s->codes_s, &s->ids_s, &s->keys64, &s->parent, &s->counter,
+                   &s->sort_tmp, &s->pe, &s->plen, &s->pcdf, &s->scan_tmp, &s->ecls, &s->epos, &s->elist, &s->ecode,
+                   &s->ecode_s, &s->elist_s, &s->ekeys, &s->eparent, &s->ecounter, &s->etree, &s->ebounds, &s->edepth,
+                   &s->ck_tri, &s->ck_x, &s->ck_vis, &s->camacc};
+    for (Buf* b : bufs) b->release();
+    s->counters.release();
+    for (auto& e : s->evs) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    s->evs.clear();
+}
+
+static bool valid_camera(const drCamera* c) {
+    if (!c || c->width <= 0 || c->height <= 0 || !(c->fov_y_deg > 0.0f && c->fov_y_deg < 180.0f) || !(c->near_clip > 0.0f))
+        return false;
+    bool full = c->window[0] == 0 && c->window[1] == 0 && c->window[2] == 0 && c->window[3] == 0;
+    if (!full && (c->window[0] < 0 || c->window[1] < 0 || c->window[2] > c->width || c->window[3] > c->height ||
+                  c->window[0] >= c->window[2] || c->window[1] >= c->window[3]))
+        return false;
+    float d[3] = {c->look_at[0] - c->position[0], c->look_at[1] - c->position[1], c->look_at[2] - c->position[2]};
+    return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0.0f;
+}
+
+static bool valid_options(const drRenderOptions* o) {
+    return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0;
+}
+
+static ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {
+    ViewKey k{};
+    for (int i = 0; i < 3; ++i) {
+        k.cam[i] = c.position[i];
+        k.cam[3 + i] = c.look_at[i];
+        k.cam[6 + i] = c.up[i];
+    }
+    k.fov = c.fov_y_deg;
+    k.nearc = c.near_clip;
+    k.w = c.width;
+    k.h = c.height;
+    for (int i = 0; i < 4; ++i) k.win[i] = c.window[i];
+    k.spp = o.spp;
+    k.depth = o.max_depth;
+    k.seed = o.seed;
+    k.view = o.view_id;
+    k.mask = o.unit_mask;
+    k.version = s->version;
+    return k;
+}
+
+extern "C" {
+
+const char* drGetErrorString(drStatus s) {
+    switch (s) {
+        case DR_SUCCESS: return "success";
+        case DR_ERROR_INVALID_VALUE: return "invalid value";
+        case DR_ERROR_OUT_OF_MEMORY: return "out of device memory";
+        case DR_ERROR_DEVICE: return "device error";
+        case DR_ERROR_UNSUPPORTED: return "unsupported scene";
+    }
+    return "unknown status";
+}
+
+drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
+    if (!out || !d) return DR_ERROR_INVALID_VALUE;
+    *out = nullptr;
+    if (d->num_vertices < 3 || d->num_triangles < 1 || !d->vertices || !d->indices || !d->albedo || !d->emission)
+        return DR_ERROR_INVALID_VALUE;
+    int V = d->num_vertices, T = d->num_triangles;
+    std::vector<int> I(3 * (size_t)T);
+    std::vector<float> emi(T);
+    API_CHECK(hipMemcpyAsync(I.data(), d->indices, sizeof(int) * I.size(), hipMemcpyDeviceToHost, st));
+    API_CHECK(hipMemcpyAsync(emi.data(), d->emission, sizeof(float) * T, hipMemcpyDeviceToHost, st));
+    API_CHECK(hipStreamSynchronize(st));
+    for (int v : I)
+        if (v < 0 || v >= V) return DR_ERROR_INVALID_VALUE;
+    for (int t = 0; t < T; ++t)
+        if (I[3 * t] == I[3 * t + 1] || I[3 * t + 1] == I[3 * t + 2] || I[3 * t] == I[3 * t + 2]) return DR_ERROR_INVALID_VALUE;
+    // unique undirected edges, sorted by (min vertex, max vertex), faces in index order
+    struct K { int a, b, f; };
+    std::vector<K> ks;
+    ks.reserve(3 * (size_t)T);
+    for (int f = 0; f < T; ++f)
+        for (int j = 0; j < 3; ++j) {
+            int a = I[3 * f + j], b = I[3 * f + (j + 1) % 3];
+            ks.push_back({std::min(a, b), std::max(a, b), f});
+        }
+    std::sort(ks.begin(), ks.end(), [](const K& x, const K& y) {
+        if (x.a != y.a) return x.a < y.a;
+        if (x.b != y.b) return x.b < y.b;
+        return x.f < y.f;
+    });
+    std::vector<int4> edges;
+    for (size_t i = 0; i < ks.size();) {
+        size_t j = i;
+        while (j < ks.size() && ks[j].a == ks[i].a && ks[j].b == ks[i].b) ++j;
+        if (j - i > 2) return DR_ERROR_UNSUPPORTED;
+        edges.push_back(make_int4(ks[i].a, ks[i].b, ks[i].f, j - i == 2 ? ks[i + 1].f : -1));
+        i = j;
+    }
+    std::vector<int> lights;
+    for (int t = 0; t < T; ++t)
+        if (emi[t] > 0.0f) lights.push_back(t);
+    drScene_t* s = new drScene_t();
+    s->V = V;
+    s->T = T;
+    s->E = (int)edges.size();
+    s->L = (int)lights.size();
+    s->smooth = d->normals != nullptr;
+    s->two_sided = d->emission_two_sided ? 1 : 0;
+    s->background = d->background;
+    API_CHECK(hipGetDevice(&s->device));
+    auto fail = [&](drStatus e) {
+        release_all(s);
+        delete s;
+        return e;
+    };
+#define TRY_ALLOC(buf, n) \
+    if ((buf).ensure(n) != hipSuccess) return fail(DR_ERROR_OUT_OF_MEMORY)
+    TRY_ALLOC(s->P, sizeof(float) * 3 * V);
+    TRY_ALLOC(s->I, sizeof(int) * 3 * T);
+    if (s->smooth) TRY_ALLOC(s->N, sizeof(float) * 3 * V);
+    TRY_ALLOC(s->alb, sizeof(float) * T);
+    TRY_ALLOC(s->emi, sizeof(float) * T);
+    TRY_ALLOC(s->tri, sizeof(float4) * 3 * T);
+    TRY_ALLOC(s->bvh, sizeof(BvhNode) * std::max(T - 1, 1));
+    TRY_ALLOC(s->edges, sizeof(int4) * s->E);
+    TRY_ALLOC(s->ekind, std::max(s->E, 1));
+    TRY_ALLOC(s->lights, sizeof(int) * std::max(s->L, 1));
+    TRY_ALLOC(s->lcdf, sizeof(double) * std::max(s->L, 1));
+    TRY_ALLOC(s->scal, sizeof(float) * 16);
+    TRY_ALLOC(s->err, sizeof(int));
+    TRY_ALLOC(s->codes, sizeof(uint32_t) * T);
+    TRY_ALLOC(s->ids, sizeof(int) * T);
+    TRY_ALLOC(s->codes_s, sizeof(uint32_t) * T);
+    TRY_ALLOC(s->ids_s, sizeof(int) * T);
+    TRY_ALLOC(s->keys64, sizeof(uint64_t) * T);
+    TRY_ALLOC(s->parent, sizeof(int) * 2 * T);
+    TRY_ALLOC(s->counter, sizeof(int2) * T);
+#undef TRY_ALLOC
+    if (hipMemcpyAsync(s->P.p, d->vertices, sizeof(float) * 3 * V, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->I.p, I.data(), sizeof(int) * 3 * T, hipMemcpyHostToDevice, st) != hipSuccess ||
+        (s->smooth && hipMemcpyAsync(s->N.p, d->normals, sizeof(float) * 3 * V, hipMemcpyDeviceToDevice, st) != hipSuccess) ||
+        hipMemcpyAsync(s->alb.p, d->albedo, sizeof(float) * T, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->emi.p, d->emission, sizeof(float) * T, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->edges.p, edges.data(), sizeof(int4) * s->E, hipMemcpyHostToDevice, st) != hipSuccess ||
+        (s->L && hipMemcpyAsync(s->lights.p, lights.data(), sizeof(int) * s->L, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipMemsetAsync(s->err.p, 0, sizeof(int), st) != hipSuccess)
+        return fail(DR_ERROR_DEVICE);
+    drStatus r = build_scene_static(s, st);
+    if (r != DR_SUCCESS) return fail(r);
+    s->last_stream = st;
+    *out = s;
+    return DR_SUCCESS;
+}
+
+drStatus drSceneUpdateVertices(drScene s, const float* vertices, hipStream_t st) {
+    if (!s || !vertices) return DR_ERROR_INVALID_VALUE;
+    API_CHECK(hipMemcpyAsync(s->P.p, vertices, sizeof(float) * 3 * s->V, hipMemcpyDeviceToDevice, st));
+    s->version++;
+    s->tree_valid = false;
+    s->ck_valid = false;
+    s->last_stream = st;
+    return build_scene_static(s, st);
+}
+
+drStatus drSceneGetInfo(drScene s, int32_t* nv, int32_t* nt, int32_t* ne) {
+    if (!s) return DR_ERROR_INVALID_VALUE;
+    if (nv) *nv = s->V;
+    if (nt) *nt = s->T;
+    if (ne) *ne = s->E;
+    return DR_SUCCESS;
+}
+
+static drStatus ensure_checkpoints(drScene s, long M) {
+    if (s->ck_tri.ensure(sizeof(int) * 2 * (size_t)M) != hipSuccess ||
+        s->ck_x.ensure(sizeof(float) * 6 * (size_t)M) != hipSuccess || s->ck_vis.ensure((size_t)M) != hipSuccess)
+        return DR_ERROR_OUT_OF_MEMORY;
+    return DR_SUCCESS;
+}
+
+drStatus drRender(drScene s, const drCamera* c, const drRenderOptions* o, float* image, hipStream_t st) {
+    if (!s || !valid_camera(c) || !valid_options(o) || !image) return DR_ERROR_INVALID_VALUE;
+    Cam cam = make_cam(*c);
+    long M = (long)(cam.x1 - cam.x0) * (cam.y1 - cam.y0) * o->spp;
+    if (M >= (1L << 31)) return DR_ERROR_INVALID_VALUE;
+    drStatus r = ensure_checkpoints(s, M);
+    if (r != DR_SUCCESS) return r;
+    r = launch_forward(s, cam, *o, image, st);
+    if (r != DR_SUCCESS) return r;
+    s->ck_key = make_key(s, *c, *o);
+    s->ck_valid = true;
+    s->last_stream = st;
+    return DR_SUCCESS;
+}
+
+drStatus drRenderBackward(drScene s, const drCamera* c, const drRenderOptions* o, const float* d_image, float* d_vertices,
+                          float* d_albedo, float* d_camera, hipStream_t st) {
+    if (!s || !valid_camera(c) || !valid_options(o) || !d_image) return DR_ERROR_INVALID_VALUE;
+    Cam cam = make_cam(*c);
+    long npix = (long)(cam.x1 - cam.x0) * (cam.y1 - cam.y0);
+    long M = npix * o->spp;
+    if (M >= (1L << 31)) return DR_ERROR_INVALID_VALUE;
+    ViewKey key = make_key(s, *c, *o);
+    drStatus r;
+    if (!(s->ck_valid && s->ck_key == key)) {
+        // no matching forward pass: recompute the checkpoints
+        r = ensure_checkpoints(s, M);
+        if (r != DR_SUCCESS) return r;
+        Buf img;
+        if (img.ensure(sizeof(float) * npix) != hipSuccess) return DR_ERROR_OUT_OF_MEMORY;
+        r = launch_forward(s, cam, *o, img.as<float>(), st);
+        (void)hipStreamSynchronize(st);
+        img.release();
+        if (r != DR_SUCCESS) return r;
+        s->ck_key = key;
+        s->ck_valid = true;
+    }
+    uint32_t terms = o->terms ? o->terms : DR_TERM_ALL;
+    bool need_tree = o->max_depth >= 1 && (terms & DR_TERM_SECONDARY);
+    ViewKey tkey = key;
+    tkey.spp = 0; tkey.seed = 0; tkey.view = 0; tkey.mask = nullptr; tkey.depth = 0;
+    r = build_view_edges(s, cam, tkey, need_tree, st);
+    if (r != DR_SUCCESS) return r;
+    r = launch_backward(s, cam, *o, d_image, d_vertices, d_albedo, d_camera, st);
+    s->last_stream = st;
+    return r;
+}
+
+drStatus drSetProfiling(drScene s, int32_t events, int32_t counters) {
+    if (!s) return DR_ERROR_INVALID_VALUE;
+    s->prof_events = events != 0;
+    s->prof_counters = counters != 0;
+    if (s->prof_counters) {
+        API_ALLOC(s->counters, 24 * sizeof(unsigned long long));
+        API_CHECK(hipMemset(s->counters.p, 0, 24 * sizeof(unsigned long long)));
+    }
+    return DR_SUCCESS;
+}
+
+drStatus drGetProfile(drScene s, drProfile* out, int32_t reset) {
+    if (!s || !out) return DR_ERROR_INVALID_VALUE;
+    API_CHECK(hipStreamSynchronize(s->last_stream));
+    std::memset(out, 0, sizeof(*out));
+    for (auto& e : s->evs) {
+        float ms = 0.0f;
+        API_CHECK(hipEventElapsedTime(&ms, e.a, e.b));
+        if (e.kind == 0) out->forward_ms += ms;
+        else if (e.kind == 1) out->primary_ms += ms;
+        else out->backward_ms += ms;
+    }
+    out->forward_launches = s->launches[0];
+    out->primary_launches = s->launches[1];
+    out->backward_launches = s->launches[2];
+    if (s->counters.p) {
+        unsigned long long c[24];
+        API_CHECK(hipMemcpy(c, s->counters.p, sizeof(c), hipMemcpyDeviceToHost));
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < 5; ++i) out->counts[k][i] = (int64_t)c[8 * k + i];
+    }
+    if (reset) {
+        for (auto& e : s->evs) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        s->evs.clear();
+        s->launches[0] = s->launches[1] = s->launches[2] = 0;
+        if (s->counters.p) API_CHECK(hipMemset(s->counters.p, 0, 24 * sizeof(unsigned long long)));
+    }
+    return DR_SUCCESS;
+}
+
+drStatus drGetLastDeviceError(drScene s) {
+    if (!s) return DR_ERROR_INVALID_VALUE;
+    int e = 0;
+    API_CHECK(hipStreamSynchronize(s->last_stream));
+    API_CHECK(hipMemcpy(&e, s->err.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) {
+        API_CHECK(hipMemset(s->err.p, 0, sizeof(int)));
+        return DR_ERROR_DEVICE;
+    }
+    return DR_SUCCESS;
+}
+
+drStatus drSceneDestroy(drScene s) {
+    if (!s) return DR_ERROR_INVALID_VALUE;
+    (void)hipStreamSynchronize(s->last_stream);
+    release_all(s);
+    delete s;
+    return DR_SUCCESS;
+}
+
+}  // extern "C"

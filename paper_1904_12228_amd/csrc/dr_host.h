@@ -1,0 +1,96 @@
+// Host-side scene object and the launch entry points shared by the
+// library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/diffrt.h"
+#include "dr_common.h"
+
+namespace dr {
+
+// Device buffer that grows on demand and is freed with the scene.
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n) {
+        if (n <= bytes) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) bytes = n;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct ViewKey {
+    float cam[9], fov, nearc;
+    int w, h, win[4];
+    int spp, depth;
+    uint64_t seed;
+    uint32_t view;
+    const uint8_t* mask;
+    uint64_t version;
+    bool operator==(const ViewKey& o) const;
+};
+
+}  // namespace dr
+
+struct drScene_t {
+    int V = 0, T = 0, E = 0, L = 0;
+    bool smooth = false;
+    int two_sided = 0;
+    float background = 0.0f;
+    float diag = 0.0f, tmin = 0.0f, atot = 0.0f;
+    uint64_t version = 0;            // bumps on every vertex update
+    // scene data
+    dr::Buf P, I, N, alb, emi, tri, bvh, edges, ekind, lights, lcdf, scal, err;
+    // BVH build scratch
+    dr::Buf codes, ids, codes_s, ids_s, keys64, parent, counter, sort_tmp;
+    // per-view edge data
+    dr::Buf pe, plen, pcdf, scan_tmp, ecls, epos, elist, ecode, ecode_s, elist_s, ekeys, eparent, ecounter, etree,
+        ebounds, edepth;
+    int n1 = 0, n2 = 0;
+    dr::ViewKey tree_key{};
+    bool tree_valid = false;
+    // checkpoints of the last forward pass
+    dr::Buf ck_tri, ck_x, ck_vis;
+    dr::ViewKey ck_key{};
+    bool ck_valid = false;
+    // camera adjoint accumulator (f, r, u, c: 12 floats)
+    dr::Buf camacc;
+    hipStream_t last_stream = nullptr;
+    int device = 0;
+    // measurement
+    bool prof_events = false, prof_counters = false;
+    struct EvPair { hipEvent_t a, b; int kind; };
+    std::vector<EvPair> evs;
+    dr::Buf counters;                  // [8] uint64
+    int64_t launches[3] = {0, 0, 0};
+
+    dr::SceneView view() const;
+};
+
+namespace dr {
+
+// dr_build.hip
+drStatus build_scene_static(drScene_t* s, hipStream_t st);   // kinds, lights, triangles, BVH
+drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool need_tree, hipStream_t st);
+Cam make_cam(const drCamera& c);
+
+// dr_render.hip
+drStatus launch_forward(drScene_t* s, const Cam& cam, const drRenderOptions& o, float* image, hipStream_t st);
+drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o, const float* d_image,
+                         float* d_vertices, float* d_albedo, float* d_camera, hipStream_t st);
+
+}  // namespace dr

@@ -1,0 +1,133 @@
+// Light transport on the device (forward values): hit points, shading
+// normals, next-event estimation and the radiance of a path suffix, with the
+// thesis's setting (Ch. 5): Lambertian surfaces, triangle area lights.
+// Readings where the thesis is silent: one light triangle picked by area and
+// a point by the square-root warp; next-event estimation only (emission found
+// by continuation rays is not added); cosine-weighted continuation around the
+// shading normal; emitters radiate along their geometric normal.
+#pragma once
+#include "dr_trace.h"
+
+namespace dr {
+
+struct TriGeom { v3 p0, e1, e2; };
+
+__device__ inline TriGeom tri_geom(const SceneView& s, int id) {
+    float4 a = s.tri[3 * id], b = s.tri[3 * id + 1], c = s.tri[3 * id + 2];
+    return {{a.x, a.y, a.z}, {a.w, b.x, b.y}, {b.z, b.w, c.x}};
+}
+
+// Point where the ray meets the triangle's plane (moves with the ray and the
+// triangle under differentiation).
+__device__ inline v3 hit_point(const TriGeom& g, v3 o, v3 d) {
+    v3 n = cross(g.e1, g.e2);
+    float t = dot(g.p0 - o, n) / dot(d, n);
+    return o + d * t;
+}
+
+// Shading normal at x (unoriented): interpolated vertex normals, or the
+// geometric normal for flat scenes.
+__device__ inline v3 shading_normal(const SceneView& s, int id, const TriGeom& g, v3 x) {
+    v3 n = cross(g.e1, g.e2);
+    if (!s.N) return nrm(n);
+    v3 w = x - g.p0;
+    float nn = dot(n, n);
+    float b1 = dot(cross(w, g.e2), n) / nn;
+    float b2 = dot(cross(g.e1, w), n) / nn;
+    int i0 = s.I[3 * id], i1 = s.I[3 * id + 1], i2 = s.I[3 * id + 2];
+    v3 N0 = ld3(s.N, i0), N1 = ld3(s.N, i1), N2 = ld3(s.N, i2);
+    return nrm(N0 * (1.0f - b1 - b2) + N1 * b1 + N2 * b2);
+}
+
+__device__ inline float emitted(const SceneView& s, int id, bool front) {
+    float e = s.emi[id];
+    if (e <= 0.0f) return 0.0f;
+    return (front || s.two_sided) ? e : 0.0f;
+}
+
+__device__ inline int pick_cdf(const double* cdf, int n, float u) {
+    // first index with cdf[i] > u
+    int lo = 0, hi = n - 1;
+    double ud = (double)u;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cdf[mid] > ud) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+struct NeeSample {
+    v3 w;        // unit direction towards the light point
+    float K;     // radiance * solid-angle factor / pi (0: no contribution)
+    float r;     // distance to the light point
+};
+
+// Light sample for NEE at x with shading normal ns; visibility not tested.
+__device__ inline NeeSample nee_sample(const SceneView& s, float4 u, v3 x, v3 ns) {
+    NeeSample q{{0, 0, 0}, 0.0f, 0.0f};
+    if (s.L == 0) return q;
+    int li = pick_cdf(s.lcdf, s.L, u.x);
+    int lt = s.lights[li];
+    TriGeom g = tri_geom(s, lt);
+    float su = sqrtf(u.y);
+    v3 y = g.p0 + g.e1 * (su * (1.0f - u.z)) + g.e2 * (su * u.z);
+    v3 w = y - x;
+    float r2 = dot(w, w), r = sqrtf(r2);
+    v3 wh = w * (1.0f / r);
+    v3 nl = nrm(cross(g.e1, g.e2));
+    float cy = -dot(nl, wh);
+    if (s.two_sided) cy = fabsf(cy);
+    float cp = dot(ns, wh);
+    q.w = wh;
+    q.r = r;
+    if (cp <= 0.0f || cy <= 0.0f) return q;
+    q.K = s.emi[lt] * cy / r2 * s.atot / kPi;
+    return q;
+}
+
+__device__ inline v3 cosine_dir(v3 n, float u0, float u1) {
+    v3 t1, t2;
+    onb(n, t1, t2);
+    float r = sqrtf(u0), ph = 2.0f * kPi * u1;
+    float sp, cp;
+    sincosf(ph, &sp, &cp);
+    return t1 * (r * cp) + t2 * (r * sp) + n * sqrtf(1.0f - u0);
+}
+
+// Radiance arriving along a ray: emission at the first hit, then NEE at path
+// vertices 1..budget with cosine continuation between them. camera: misses
+// return the background and t_min is the near clip.
+__device__ inline float radiance(const SceneView& s, const Rng& rng, int base, v3 o, v3 d, float tmin, bool camera,
+                                 int budget, int* stk, int stride, Work* wk = nullptr) {
+    Hit h = trace_closest(s, o, d, tmin, 3.0e38f, stk, stride, wk);
+    if (h.tri < 0) return camera ? s.background : 0.0f;
+    int tri = h.tri;
+    TriGeom g = tri_geom(s, tri);
+    v3 x = hit_point(g, o, d);
+    bool front = dot(d, cross(g.e1, g.e2)) < 0.0f;
+    float L = emitted(s, tri, front);
+    float beta = 1.0f;
+    for (int k = 1; k <= budget; ++k) {
+        v3 ns = shading_normal(s, tri, g, x);
+        if (!front) ns = -ns;
+        float rho = s.alb[tri];
+        if (rho == 0.0f) break;
+        NeeSample q = nee_sample(s, rng.block(base + 2 * k - 1), x, ns);
+        if (q.K > 0.0f && !trace_any(s, x, q.w, s.tmin, q.r * (1.0f - kShadowEnd), stk, stride, wk))
+            L += beta * rho * dot(ns, q.w) * q.K;
+        if (k == budget) break;
+        float4 ub = rng.block(base + 2 * k);
+        v3 w = cosine_dir(ns, ub.x, ub.y);
+        if (dot(ns, w) <= 0.0f) break;
+        Hit h2 = trace_closest(s, x, w, s.tmin, 3.0e38f, stk, stride, wk);
+        if (h2.tri < 0) break;
+        beta *= rho;
+        tri = h2.tri;
+        g = tri_geom(s, tri);
+        x = hit_point(g, x, w);
+        front = dot(w, cross(g.e1, g.e2)) < 0.0f;
+    }
+    return L;
+}
+
+}  // namespace dr

@@ -1,0 +1,744 @@
+// Forward and backward kernels of the edge-sampling differentiable path
+// tracer (thesis Ch. 5). One lane per unit: a unit is one pixel sample (its
+// path, interior adjoint and one secondary edge sample per path vertex) plus
+// one primary edge sample. Blocks are one 64-lane wave; each lane's BVH
+// traversal stack lives in LDS.
+//
+// Measure convention of the interior term: the screen sample, every sampled
+// world direction and every sampling pdf are held fixed (the integrals are
+// over screen space and over the sphere of directions at each vertex); hit
+// points move by ray-plane intersection with their triangles. The boundary
+// terms use the matching measures: screen-space edges (eq. mc) and
+// direction-space edges at each vertex (eq. dirac_3d_edge in the solid-angle
+// measure; its endpoint terms equal the thesis's area form exactly).
+#include <cstdlib>
+
+#include "dr_host.h"
+#include "dr_path.h"
+
+namespace dr {
+
+constexpr int BS = 64;
+
+struct RenderArgs {
+    int spp, depth, M, Ww;
+    int debug_unit;    // unit whose secondary samples are printed (-1: none)
+    unsigned long long* counters;   // [5] work counters, or null
+    uint32_t k0, k1, view, terms;
+    const uint8_t* mask;
+    int* ck_tri;       // [2][M]
+    float* ck_x;       // [2][M][3]
+    uint8_t* ck_vis;   // [M]
+};
+
+__device__ inline void unit_pixel(const Cam& k, const RenderArgs& a, int m, int& pix, int& px, int& py, uint32_t& sid) {
+    pix = m / a.spp;
+    int smp = m - pix * a.spp;
+    int pxr = pix % a.Ww, pyr = pix / a.Ww;
+    px = k.x0 + pxr;
+    py = k.y0 + pyr;
+    sid = ((uint32_t)py * (uint32_t)k.W + (uint32_t)px) * (uint32_t)a.spp + (uint32_t)smp;
+}
+
+__device__ inline void flush_work(const Work& w, unsigned long long* c) {
+    if (!c) return;
+    uint32_t v[5] = {w.nodes, w.tris, w.tnodes, w.atom, w.rays};
+    for (int i = 0; i < 5; ++i) {
+        uint32_t t = v[i];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, BS);
+        if (threadIdx.x == 0 && t) atomicAdd(&c[i], (unsigned long long)t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a, float* __restrict__ image, int reduce) {
+    __shared__ int stk[kStackDepth * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    int m = blockIdx.x * BS + lane;
+    float L = 0.0f;
+    int pix = 0;
+    Work wk;
+    Work* pw = a.counters ? &wk : nullptr;
+    if (m < a.M) {
+        int px, py;
+        uint32_t sid;
+        unit_pixel(k, a, m, pix, px, py, sid);
+        bool act = !a.mask || a.mask[m];
+        int ckt0 = -1, ckt1 = -1;
+        v3 ckx0 = {0, 0, 0}, ckx1 = {0, 0, 0};
+        uint8_t vis = 0;
+        if (act) {
+            Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
+            float4 j = rc.block(0);
+            v3 d = cam_dir(k, px + j.x, py + j.y);
+            Hit h = trace_closest(s, k.c, d, k.nearc, 3.0e38f, my, BS, pw);
+            if (h.tri < 0) {
+                L = s.background;
+            } else {
+                int tri = h.tri;
+                TriGeom g = tri_geom(s, tri);
+                v3 x = hit_point(g, k.c, d);
+                bool front = dot(d, cross(g.e1, g.e2)) < 0.0f;
+                L = emitted(s, tri, front);
+                ckt0 = tri;
+                ckx0 = x;
+                float beta = 1.0f;
+                for (int kk = 1; kk <= a.depth; ++kk) {
+                    v3 ns = shading_normal(s, tri, g, x);
+                    if (!front) ns = -ns;
+                    float rho = s.alb[tri];
+                    if (rho == 0.0f) break;
+                    NeeSample q = nee_sample(s, rc.block(2 * kk - 1), x, ns);
+                    if (q.K > 0.0f && !trace_any(s, x, q.w, s.tmin, q.r * (1.0f - kShadowEnd), my, BS, pw)) {
+                        L += beta * rho * dot(ns, q.w) * q.K;
+                        vis |= (uint8_t)(1u << (kk - 1));
+                    }
+                    if (kk == a.depth) break;
+                    float4 ub = rc.block(2 * kk);
+                    v3 w = cosine_dir(ns, ub.x, ub.y);
+                    if (dot(ns, w) <= 0.0f) break;
+                    Hit h2 = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, pw);
+                    if (h2.tri < 0) break;
+                    beta *= rho;
+                    tri = h2.tri;
+                    g = tri_geom(s, tri);
+                    x = hit_point(g, x, w);
+                    front = dot(w, cross(g.e1, g.e2)) < 0.0f;
+                    if (kk == 1) { ckt1 = tri; ckx1 = x; }
+                }
+            }
+        }
+        if (a.ck_tri) {
+            a.ck_tri[m] = ckt0;
+            a.ck_tri[a.M + m] = ckt1;
+            float* cx = a.ck_x + 3 * (size_t)m;
+            cx[0] = ckx0.x; cx[1] = ckx0.y; cx[2] = ckx0.z;
+            float* cy = a.ck_x + 3 * ((size_t)a.M + m);
+            cy[0] = ckx1.x; cy[1] = ckx1.y; cy[2] = ckx1.z;
+            a.ck_vis[m] = vis;
+        }
+    }
+    flush_work(wk, a.counters);
+    float v = L / (float)a.spp;
+    if (reduce) {
+        // a.spp divides 64: lanes of one pixel are consecutive, reduce in-wave
+        for (int off = a.spp >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, BS);
+        if (m < a.M && (lane % a.spp) == 0) image[pix] = v;
+    } else if (m < a.M) {
+        atomicAdd(&image[pix], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint helpers
+// ---------------------------------------------------------------------------
+struct CamAcc { v3 f, r, u, c; };
+
+__device__ inline void atomic_add3(float* p, int i, v3 v) {
+    if (v.x != 0.0f) atomicAdd(&p[3 * i], v.x);
+    if (v.y != 0.0f) atomicAdd(&p[3 * i + 1], v.y);
+    if (v.z != 0.0f) atomicAdd(&p[3 * i + 2], v.z);
+}
+
+// Projection to pixels and its adjoint.
+__device__ inline void project(const Cam& k, v3 P, float& sx, float& sy) {
+    v3 q = P - k.c;
+    float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);
+    sx = (1.0f + xc / (z * (k.asp * k.th))) * (k.W * 0.5f);
+    sy = (1.0f - yc / (z * k.th)) * (k.H * 0.5f);
+}
+
+__device__ inline v3 project_adj(const Cam& k, v3 P, float gsx, float gsy, CamAcc& ca) {
+    v3 q = P - k.c;
+    float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);
+    float ax = k.W * 0.5f / (k.asp * k.th), ay = k.H * 0.5f / k.th;
+    float gxc = gsx * ax / z;
+    float gyc = -gsy * ay / z;
+    float gz = -gsx * ax * xc / (z * z) + gsy * ay * yc / (z * z);
+    v3 gq = k.f * gz + k.r * gxc + k.u * gyc;
+    ca.f += q * gz;
+    ca.r += q * gxc;
+    ca.u += q * gyc;
+    ca.c -= gq;
+    return gq;
+}
+
+// Points defining the edge equation alpha (eq. edge_equation): the endpoints,
+// except that an endpoint behind the near plane is replaced by the edge point
+// at depth zd = max(near, half the other endpoint's depth). Any two points of
+// the edge in front of the camera give the same projected line, hence the same
+// boundary term; this choice keeps the projection well conditioned.
+__device__ inline v3 alpha_point(const Cam& k, v3 a, v3 b, float za, float zb) {
+    float zd = fmaxf(k.nearc, 0.5f * zb);
+    return a + (b - a) * ((zd - za) / (zb - za));
+}
+
+// Adjoint of a* = a + (b - a) s, s = (zd - za)/(zb - za), zd = max(near, zb/2).
+__device__ inline void nearclip_adj(const Cam& k, v3 a, v3 b, v3 g, v3& ga, v3& gb, CamAcc& ca) {
+    float za = dot(a - k.c, k.f), zb = dot(b - k.c, k.f);
+    float D = zb - za;
+    bool half = 0.5f * zb > k.nearc;
+    float zd = half ? 0.5f * zb : k.nearc;
+    float s = (zd - za) / D;
+    ga += g * (1.0f - s);
+    gb += g * s;
+    float gs = dot(g, b - a);
+    float gza = gs * (s - 1.0f) / D, gzb = gs * ((half ? 0.5f : 0.0f) - s) / D;
+    ga += k.f * gza;
+    gb += k.f * gzb;
+    ca.c -= k.f * (gza + gzb);
+    ca.f += (a - k.c) * gza + (b - k.c) * gzb;
+}
+
+// Adjoint of x = o + d t, t = (p0 - o).n / (d.n), n = e1 x e2.
+__device__ inline void ray_plane_adj(const TriGeom& g, v3 o, v3 d, v3 gx, v3& go, v3& gd, v3& gp0, v3& gp1, v3& gp2) {
+    v3 n = cross(g.e1, g.e2);
+    float den = dot(d, n);
+    float num = dot(g.p0 - o, n);
+    float t = num / den;
+    go += gx;
+    gd += gx * t;
+    float gt = dot(gx, d);
+    float gnum = gt / den, gden = -gt * t / den;
+    gp0 += n * gnum;
+    go -= n * gnum;
+    v3 gn = (g.p0 - o) * gnum + d * gden;
+    gd += n * gden;
+    v3 ge1 = cross(g.e2, gn), ge2 = cross(gn, g.e1);
+    gp1 += ge1;
+    gp2 += ge2;
+    gp0 -= ge1 + ge2;
+}
+
+// Adjoint of the shading normal (unoriented) w.r.t. the hit point and the
+// triangle vertices; gns is dL/d(normal before orientation).
+__device__ inline void shading_normal_adj(const SceneView& s, int id, const TriGeom& g, v3 x, v3 gns, v3& gx, v3& gp0, v3& gp1,
+                                          v3& gp2) {
+    v3 n = cross(g.e1, g.e2);
+    v3 gn = {0, 0, 0}, ge1 = {0, 0, 0}, ge2 = {0, 0, 0};
+    if (!s.N) {
+        gn = nrm_adj(n, gns);
+    } else {
+        v3 w = x - g.p0;
+        float nn = dot(n, n);
+        v3 c1 = cross(w, g.e2), c2 = cross(g.e1, w);
+        float b1 = dot(c1, n) / nn, b2 = dot(c2, n) / nn;
+        int i0 = s.I[3 * id], i1 = s.I[3 * id + 1], i2 = s.I[3 * id + 2];
+        v3 N0 = ld3(s.N, i0), N1 = ld3(s.N, i1), N2 = ld3(s.N, i2);
+        v3 mv = N0 * (1.0f - b1 - b2) + N1 * b1 + N2 * b2;
+        v3 gm = nrm_adj(mv, gns);
+        float gb1 = dot(gm, N1 - N0), gb2 = dot(gm, N2 - N0);
+        float gq1 = gb1 / nn, gq2 = gb2 / nn;
+        float gnn = -(gb1 * b1 + gb2 * b2) / nn;
+        v3 gc1 = n * gq1, gc2 = n * gq2;
+        gn += c1 * gq1 + c2 * gq2 + n * (2.0f * gnn);
+        v3 gw = cross(g.e2, gc1) + cross(gc2, g.e1);
+        ge2 += cross(gc1, w);
+        ge1 += cross(w, gc2);
+        gx += gw;
+        gp0 -= gw;
+    }
+    ge1 += cross(g.e2, gn);
+    ge2 += cross(gn, g.e1);
+    gp1 += ge1;
+    gp2 += ge2;
+    gp0 -= ge1 + ge2;
+}
+
+__device__ inline float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, BS);
+    return v;
+}
+
+__device__ inline void flush_cam(const CamAcc& ca, float* camacc) {
+    float v[12] = {ca.f.x, ca.f.y, ca.f.z, ca.r.x, ca.r.y, ca.r.z, ca.u.x, ca.u.y, ca.u.z, ca.c.x, ca.c.y, ca.c.z};
+    for (int i = 0; i < 12; ++i) {
+        float t = wave_sum(v[i]);
+        if (threadIdx.x == 0 && t != 0.0f) atomicAdd(&camacc[i], t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// primary edge samples (eq. mc): one per unit
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
+                                                const double* __restrict__ cdf, const float* __restrict__ d_image,
+                                                float* __restrict__ dV, float* __restrict__ camacc) {
+    __shared__ int stk[kStackDepth * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    int m = blockIdx.x * BS + lane;
+    CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    Work wk;
+    Work* pw = a.counters ? &wk : nullptr;
+    double total = cdf[s.E];
+    if (m < a.M && (!a.mask || a.mask[m]) && total > 0.0) {
+        Rng rp{(uint32_t)m, a.view, kTagPedge, a.k0, a.k1};
+        float4 b0 = rp.block(0);
+        int ei = pick_cdf(cdf, s.E, b0.x);
+        PEdge p = pe[ei];
+        float t = b0.y;
+        float x = p.Ac[0] + (p.Bc[0] - p.Ac[0]) * t, y = p.Ac[1] + (p.Bc[1] - p.Ac[1]) * t;
+        int4 e = s.edges[ei];
+        v3 va = ld3(s.P, e.x), vb = ld3(s.P, e.y);
+        float za = dot(va - k.c, k.f), zb = dot(vb - k.c, k.f);
+        v3 ac = za < k.nearc ? alpha_point(k, va, vb, za, zb) : va;
+        v3 bc = zb < k.nearc ? alpha_point(k, vb, va, zb, za) : vb;
+        float Ax, Ay, Bx, By;
+        project(k, ac, Ax, Ay);
+        project(k, bc, Bx, By);
+        float dx = Ax - Bx, dy = Ay - By;
+        float nl = sqrtf(dx * dx + dy * dy);
+        float nx = (Ay - By) / nl, ny = (Bx - Ax) / nl;
+        float fu = radiance(s, rp, 0, k.c, cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), k.nearc, true, a.depth, my, BS, pw);
+        float fl = radiance(s, rp, 0, k.c, cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny), k.nearc, true, a.depth, my, BS, pw);
+        if (m == a.debug_unit)
+            printf("punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g n %.9g %.9g fu %.9g fl %.9g total %.9g\n", m, ei, x,
+                   y, Ax, Ay, Bx, By, nx, ny, fu, fl, total);
+        if (fu != fl) {
+            int ix = min(max((int)floorf(x), k.x0), k.x1 - 1);
+            int iy = min(max((int)floorf(y), k.y0), k.y1 - 1);
+            float w = d_image[(iy - k.y0) * a.Ww + (ix - k.x0)] * (fu - fl) * (float)(total / (double)a.M) / nl;
+            // d alpha / d(a, b) (eq. redner_dirac_jacobian) at the sample point
+            float gax = w * (By - y), gay = w * (x - Bx);
+            float gbx = w * (y - Ay), gby = w * (Ax - x);
+            v3 gac = project_adj(k, ac, gax, gay, ca);
+            v3 gbc = project_adj(k, bc, gbx, gby, ca);
+            v3 ga = {0, 0, 0}, gb = {0, 0, 0};
+            if (za < k.nearc) nearclip_adj(k, va, vb, gac, ga, gb, ca);
+            else ga += gac;
+            if (zb < k.nearc) nearclip_adj(k, vb, va, gbc, gb, ga, ca);
+            else gb += gbc;
+            atomic_add3(dV, e.x, ga);
+            atomic_add3(dV, e.y, gb);
+            wk.atom += 6;
+        }
+    }
+    flush_work(wk, a.counters);
+    flush_cam(ca, camacc);
+}
+
+// ---------------------------------------------------------------------------
+// edge hierarchy descent (Edge selection): one uniform per level, explicit pdf
+// ---------------------------------------------------------------------------
+__device__ inline bool vsphere_prune(const ETChild& c, v3 pc) {
+    v3 sc = pc * 0.5f;
+    float r2 = dot(pc, pc) * 0.25f;
+    const float sv[3] = {sc.x, sc.y, sc.z};
+    bool out[2], in[2];
+    for (int f = 0; f < 2; ++f) {
+        const float* lo = f == 0 ? c.hlo0 : c.hlo1;
+        const float* hi = f == 0 ? c.hhi0 : c.hhi1;
+        float d2 = 0.0f, far2 = 0.0f;
+        for (int k = 0; k < 3; ++k) {
+            float d = sv[k] < lo[k] ? lo[k] - sv[k] : (sv[k] > hi[k] ? sv[k] - hi[k] : 0.0f);
+            d2 += d * d;
+            float fa = fmaxf(fabsf(lo[k] - sv[k]), fabsf(hi[k] - sv[k]));
+            far2 += fa * fa;
+        }
+        out[f] = d2 > r2 * (1.0f + kVsphereMargin);
+        in[f] = far2 < r2 * (1.0f - kVsphereMargin);
+    }
+    return (out[0] && out[1]) || (in[0] && in[1]);
+}
+
+__device__ inline float cos_bound(const float lo[3], const float hi[3], v3 p, v3 n, float hz) {
+    v3 t1, t2;
+    onb(n, t1, t2);
+    float xl = 3e38f, xh = -3e38f, yl = 3e38f, yh = -3e38f, zh = -3e38f;
+    for (int c = 0; c < 8; ++c) {
+        v3 q = {((c & 1) ? hi[0] : lo[0]) - p.x, ((c & 2) ? hi[1] : lo[1]) - p.y, ((c & 4) ? hi[2] : lo[2]) - p.z};
+        float x = dot(t1, q), y = dot(t2, q), z = dot(n, q);
+        xl = fminf(xl, x); xh = fmaxf(xh, x);
+        yl = fminf(yl, y); yh = fmaxf(yh, y);
+        zh = fmaxf(zh, z);
+    }
+    float dx = (xl <= 0.0f && xh >= 0.0f) ? 0.0f : fminf(fabsf(xl), fabsf(xh));
+    float dy = (yl <= 0.0f && yh >= 0.0f) ? 0.0f : fminf(fabsf(yl), fabsf(yh));
+    float dxy2 = dx * dx + dy * dy;
+    if (zh <= hz) return 0.0f;
+    if (dxy2 == 0.0f) return 1.0f;
+    return zh / sqrtf(dxy2 + zh * zh);
+}
+
+struct TreeCtx {
+    const SceneView* s;
+    v3 p, n, cam;
+    int tri;
+    float hz, pad;
+};
+
+__device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, int h2, const float* plo, const float* phi) {
+    if (ref == 0) return 0.0f;
+    if (ref < 0) {
+        int4 e = q.s->edges[~ref];
+        if (e.z == q.tri || e.w == q.tri) return 0.0f;
+    }
+    if (h2 && vsphere_prune(c, q.p - q.cam)) return 0.0f;
+    float b = cos_bound(c.lo, c.hi, q.p, q.n, q.hz);
+    if (b <= 0.0f) return 0.0f;
+    const float pv[3] = {q.p.x, q.p.y, q.p.z};
+    bool in = true;
+    for (int k = 0; k < 3; ++k)
+        if (pv[k] < plo[k] - q.pad || pv[k] > phi[k] + q.pad) in = false;
+    if (in) return 1.0f;
+    v3 ctr = {(c.lo[0] + c.hi[0]) * 0.5f, (c.lo[1] + c.hi[1]) * 0.5f, (c.lo[2] + c.hi[2]) * 0.5f};
+    return c.len * b / len(ctr - q.p);
+}
+
+__device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rng& rk, float u_root, float& pdf,
+                                  bool dbg = false, Work* wk = nullptr) {
+    const ETNode* nodes = tv.nodes;
+    int node = 0;
+    float plo[3], phi[3];
+    {
+        const ETNode& r = nodes[0];
+        for (int k = 0; k < 3; ++k) { plo[k] = 3e38f; phi[k] = -3e38f; }
+        for (int c = 0; c < 2; ++c)
+            if (r.child[c] != 0)
+                for (int k = 0; k < 3; ++k) { plo[k] = fminf(plo[k], r.ch[c].lo[k]); phi[k] = fmaxf(phi[k], r.ch[c].hi[k]); }
+    }
+    pdf = 1.0f;
+    int level = -1;
+    float4 ub = make_float4(0, 0, 0, 0);
+    while (true) {
+        const ETNode& N = nodes[node];
+        if (wk) wk->tnodes++;
+        int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
+        float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
+        float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
+        float tot = w0 + w1;
+        if (!(tot > 0.0f)) return -1;
+        float u;
+        if (level < 0) u = u_root;
+        else {
+            if (level >= kMaxLevels) { atomicOr(q.s->err, kErrTreeDepth); return -1; }
+            if ((level & 3) == 0) ub = rk.block(1 + (level >> 2));
+            int c = level & 3;
+            u = c == 0 ? ub.x : (c == 1 ? ub.y : (c == 2 ? ub.z : ub.w));
+        }
+        float p0 = w0 / tot;
+        int side = u < p0 ? 0 : 1;
+        pdf *= side == 0 ? p0 : w1 / tot;
+        if (dbg) printf("  level %d node %d w0 %.9g w1 %.9g u %.9g side %d\n", level, node, w0, w1, u, side);
+        int ref = N.child[side];
+        if (ref < 0) return ~ref;
+        for (int k = 0; k < 3; ++k) { plo[k] = N.ch[side].lo[k]; phi[k] = N.ch[side].hi[k]; }
+        node = ref;
+        ++level;
+    }
+}
+
+__device__ inline bool silhouette_from(const SceneView& s, int4 e, v3 q) {
+    v3 pa = ld3(s.P, e.x);
+    v3 w = q - pa;
+    TriGeom g0 = tri_geom(s, e.z), g1 = tri_geom(s, e.w);
+    float s0 = dot(cross(g0.e1, g0.e2), w), s1 = dot(cross(g1.e1, g1.e2), w);
+    return (s0 > 0.0f) != (s1 > 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// backward over paths: secondary edges at every vertex + interior adjoint
+// ---------------------------------------------------------------------------
+template <int MAXD>
+__global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs a, TreeView tv, const float* __restrict__ d_image,
+                                                 float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc) {
+    __shared__ int stk[kStackDepth * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    int m = blockIdx.x * BS + lane;
+    CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    Work wk;
+    Work* pw = a.counters ? &wk : nullptr;
+    if (m < a.M && (!a.mask || a.mask[m]) && a.depth >= 1 && a.ck_tri[m] >= 0) {
+        int pix, px, py;
+        uint32_t sid;
+        unit_pixel(k, a, m, pix, px, py, sid);
+        float W0 = d_image[pix] / (float)a.spp;
+        Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
+        float4 j = rc.block(0);
+        float sx = px + j.x, sy = py + j.y;
+        float ndx = 2.0f * sx / k.W - 1.0f, ndy = 1.0f - 2.0f * sy / k.H;
+        v3 d0 = k.f + k.r * (ndx * k.asp * k.th) + k.u * (ndy * k.th);
+        uint8_t vis = a.ck_vis[m];
+        // ---- rebuild the path's vertices
+        int tri[MAXD];
+        v3 org[MAXD], dir[MAXD], xs[MAXD], ns[MAXD], wy[MAXD], wc[MAXD];
+        float sg[MAXD], rho[MAXD], beta[MAXD], K[MAXD], cc[MAXD];
+        int nv = 0;
+        {
+            int t = a.ck_tri[m];
+            v3 o = k.c, d = d0;
+            v3 x = {a.ck_x[3 * (size_t)m], a.ck_x[3 * (size_t)m + 1], a.ck_x[3 * (size_t)m + 2]};
+            float b = 1.0f;
+#pragma unroll
+            for (int kk = 0; kk < MAXD; ++kk) {
+                if (kk >= a.depth) break;
+                TriGeom g = tri_geom(s, t);
+                float sgn = dot(d, cross(g.e1, g.e2)) < 0.0f ? 1.0f : -1.0f;
+                v3 n = shading_normal(s, t, g, x) * sgn;
+                float r = s.alb[t];
+                if (r == 0.0f) break;
+                tri[kk] = t; org[kk] = o; dir[kk] = d; xs[kk] = x; ns[kk] = n; sg[kk] = sgn; rho[kk] = r; beta[kk] = b;
+                NeeSample q = nee_sample(s, rc.block(2 * kk + 1), x, n);
+                K[kk] = ((vis >> kk) & 1) ? q.K : 0.0f;
+                wy[kk] = q.w;
+                cc[kk] = 0.0f;
+                wc[kk] = {0, 0, 0};
+                nv = kk + 1;
+                if (kk + 1 >= a.depth) break;
+                float4 ub = rc.block(2 * kk + 2);
+                v3 w = cosine_dir(n, ub.x, ub.y);
+                float c = dot(n, w);
+                if (c <= 0.0f) break;
+                int t2;
+                v3 x2;
+                if (kk + 1 < 2) {
+                    t2 = a.ck_tri[a.M + m];
+                    if (t2 < 0) break;
+                    const float* cx = a.ck_x + 3 * ((size_t)a.M + m);
+                    x2 = {cx[0], cx[1], cx[2]};
+                } else {
+                    Hit h = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, pw);
+                    if (h.tri < 0) break;
+                    t2 = h.tri;
+                    x2 = hit_point(tri_geom(s, t2), x, w);
+                }
+                if (s.alb[t2] == 0.0f) break;     // the next vertex would end the path before contributing
+                wc[kk] = w;
+                cc[kk] = c;
+                b *= r;
+                o = x; d = w; t = t2; x = x2;
+            }
+        }
+        v3 xbar[MAXD];
+#pragma unroll
+        for (int kk = 0; kk < MAXD; ++kk) xbar[kk] = {0, 0, 0};
+        // ---- secondary boundary term: one edge sample per vertex
+        if ((a.terms & DR_TERM_SECONDARY) && tv.valid) {
+#pragma unroll
+            for (int kk = 0; kk < MAXD; ++kk) {
+                if (kk >= nv) break;
+                Rng rk{sid, a.view, kTagSedge + (uint32_t)(kk + 1), a.k0, a.k1};
+                float4 b0 = rk.block(0);
+                v3 p = xs[kk], n = ns[kk];
+                TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
+                float pdf;
+                bool dbg = m == a.debug_unit;
+                int ei = tree_sample(tv, q, rk, b0.x, pdf, dbg, pw);
+                if (ei < 0) continue;
+                int4 e = s.edges[ei];
+                if (e.z == tri[kk] || e.w == tri[kk]) continue;
+                if (s.ekind[ei] == 2 && !silhouette_from(s, e, p)) continue;
+                v3 pa = ld3(s.P, e.x), pb = ld3(s.P, e.y);
+                v3 w = pa + (pb - pa) * b0.y - p;
+                if (dot(n, w) <= kHorizon * s.diag) continue;
+                v3 v0p = pa - p, v1p = pb - p;
+                v3 c = cross(v0p, v1p);
+                float cn = len(c);
+                if (cn == 0.0f) continue;
+                v3 nh = c * (1.0f / cn);
+                float wl = len(w);
+                v3 wh = w * (1.0f / wl);
+                v3 wp = nrm(wh + nh * kEps3), wm = nrm(wh - nh * kEps3);
+                int rem = a.depth - (kk + 1);
+                float Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, pw);
+                float Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, pw);
+                // the cosine is continuous across the edge; only the radiance jumps
+                float cosw = dot(n, wh);
+                float Fp = rho[kk] / kPi * cosw * Lp;
+                float Fm = rho[kk] / kPi * cosw * Lm;
+                if (Fp == Fm) continue;
+                float Wk = d_image[pix] * beta[kk] / (float)a.spp;
+                float wgt = Wk * (Fp - Fm) * len(cross(pb - pa, wh)) / (cn * wl * pdf);
+                if (dbg)
+                    printf("unit %d vertex %d tri %d p=(%.9g %.9g %.9g) n=(%.9g %.9g %.9g) edge %d pdf %.9g t %.9g Lp %.9g "
+                           "Lm %.9g cos %.9g W %.9g wgt %.9g\n",
+                           m, kk + 1, tri[kk], p.x, p.y, p.z, n.x, n.y, n.z, ei, pdf, b0.y, Lp, Lm, cosw, Wk, wgt);
+                atomic_add3(dV, e.x, cross(v1p, wh) * wgt);
+                atomic_add3(dV, e.y, cross(wh, v0p) * wgt);
+                wk.atom += 6;
+                xbar[kk] += (cross(wh, v1p) + cross(v0p, wh)) * wgt;
+            }
+        }
+        // ---- reverse sweep: interior term and propagation of vertex adjoints
+        bool interior = (a.terms & DR_TERM_INTERIOR) != 0;
+        float Aft = 0.0f;          // radiance from later vertices per unit throughput there
+        v3 carry = {0, 0, 0};      // adjoint of this vertex's position from the next ray-plane
+        v3 gd0 = {0, 0, 0};
+#pragma unroll
+        for (int kk = MAXD - 1; kk >= 0; --kk) {
+            if (kk >= nv) continue;
+            int t = tri[kk];
+            TriGeom g = tri_geom(s, t);
+            float nee_cos = dot(ns[kk], wy[kk]);
+            float Nk = rho[kk] * nee_cos * K[kk];
+            bool cont = cc[kk] > 0.0f;
+            float Ab = cont ? Aft : 0.0f;
+            v3 gns = {0, 0, 0};
+            if (interior) {
+                float gN = W0 * beta[kk];
+                float gw = cont ? W0 * beta[kk] * Ab : 0.0f;
+                float grho = gN * nee_cos * K[kk] + gw;
+                if (grho != 0.0f) atomicAdd(&dA[t], grho);
+                gns = wy[kk] * (gN * rho[kk] * K[kk]);
+                if (cont) gns += wc[kk] * (gw * rho[kk] / cc[kk]);
+            }
+            v3 gx = xbar[kk] + carry;
+            v3 gp0 = {0, 0, 0}, gp1 = {0, 0, 0}, gp2 = {0, 0, 0};
+            if (gns.x != 0.0f || gns.y != 0.0f || gns.z != 0.0f)
+                shading_normal_adj(s, t, g, xs[kk], gns * sg[kk], gx, gp0, gp1, gp2);
+            v3 go = {0, 0, 0}, gd = {0, 0, 0};
+            ray_plane_adj(g, org[kk], dir[kk], gx, go, gd, gp0, gp1, gp2);
+            int i0 = s.I[3 * t], i1 = s.I[3 * t + 1], i2 = s.I[3 * t + 2];
+            atomic_add3(dV, i0, gp0);
+            atomic_add3(dV, i1, gp1);
+            atomic_add3(dV, i2, gp2);
+            wk.atom += 10;
+            if (kk == 0) {
+                ca.c += go;
+                gd0 = gd;
+            } else {
+                carry = go;        // the ray of vertex kk starts at vertex kk-1; its direction is held fixed
+            }
+            Aft = Nk + (cont ? rho[kk] * Ab : 0.0f);
+        }
+        // camera ray direction d = f + a r + b u
+        ca.f += gd0;
+        ca.r += gd0 * (ndx * k.asp * k.th);
+        ca.u += gd0 * (ndy * k.th);
+    }
+    flush_work(wk, a.counters);
+    flush_cam(ca, camacc);
+}
+
+// dL/d(position, look_at, up) from the frame adjoints (f, r, u, c).
+__global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, float* __restrict__ d_camera) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    v3 gf = {acc[0], acc[1], acc[2]}, gr = {acc[3], acc[4], acc[5]}, gu = {acc[6], acc[7], acc[8]}, gc = {acc[9], acc[10], acc[11]};
+    v3 look = k.look, up = k.upv;
+    // u = r x f
+    gr += cross(k.f, gu);
+    gf += cross(gu, k.r);
+    // r = normalize(f x up)
+    v3 gg = nrm_adj(cross(k.f, up), gr);
+    gf += cross(up, gg);
+    v3 gup = cross(gg, k.f);
+    // f = normalize(look - c)
+    v3 gh = nrm_adj(look - k.c, gf);
+    v3 gl = gh;
+    gc -= gh;
+    d_camera[0] = gc.x; d_camera[1] = gc.y; d_camera[2] = gc.z;
+    d_camera[3] = gl.x; d_camera[4] = gl.y; d_camera[5] = gl.z;
+    d_camera[6] = gup.x; d_camera[7] = gup.y; d_camera[8] = gup.z;
+}
+
+__global__ void k_fill(float* __restrict__ p, long n, float v) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline int nblk(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Brackets one kernel launch with HIP events when profiling is on.
+struct EvScope {
+    drScene_t* s;
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    EvScope(drScene_t* s_, int kind_, hipStream_t st_) : s(s_), kind(kind_), st(st_) {
+        s->launches[kind]++;
+        if (!s->prof_events) return;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, st);
+    }
+    ~EvScope() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        s->evs.push_back({a, b, kind});
+    }
+};
+
+static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions& o) {
+    RenderArgs a;
+    a.spp = o.spp;
+    a.depth = o.max_depth;
+    a.Ww = cam.x1 - cam.x0;
+    a.M = a.Ww * (cam.y1 - cam.y0) * o.spp;
+    a.k0 = (uint32_t)(o.seed & 0xffffffffu);
+    a.k1 = (uint32_t)(o.seed >> 32);
+    a.view = o.view_id;
+    a.terms = o.terms ? o.terms : DR_TERM_ALL;
+    a.mask = o.unit_mask;
+    const char* du = std::getenv("DIFFRT_DEBUG_UNIT");
+    a.debug_unit = du ? std::atoi(du) : -1;
+    a.counters = s->prof_counters ? s->counters.as<unsigned long long>() : nullptr;
+    a.ck_tri = s->ck_tri.as<int>();
+    a.ck_x = s->ck_x.as<float>();
+    a.ck_vis = s->ck_vis.as<uint8_t>();
+    return a;
+}
+
+drStatus launch_forward(drScene_t* s, const Cam& cam, const drRenderOptions& o, float* image, hipStream_t st) {
+    RenderArgs a = make_args(s, cam, o);
+    SceneView sv = s->view();
+    bool reduce = (BS % o.spp) == 0;
+    long npix = (long)a.Ww * (cam.y1 - cam.y0);
+    if (!reduce) k_fill<<<nblk(npix, 256), 256, 0, st>>>(image, npix, 0.0f);
+    {
+        EvScope ev(s, 0, st);
+        k_forward<<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, image, reduce ? 1 : 0);
+    }
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o, const float* d_image, float* d_vertices,
+                         float* d_albedo, float* d_camera, hipStream_t st) {
+    RenderArgs a = make_args(s, cam, o);
+    SceneView sv = s->view();
+    float* dV = d_vertices;
+    float* dA = d_albedo;
+    // outputs the caller did not ask for go to scratch
+    size_t need = sizeof(float) * (3 * (size_t)s->V + s->T + 12);
+    if (s->camacc.ensure(need) != hipSuccess) return DR_ERROR_OUT_OF_MEMORY;
+    float* scratch = s->camacc.as<float>();
+    float* camacc = scratch;
+    if (!dV) dV = scratch + 12;
+    if (!dA) dA = scratch + 12 + 3 * (size_t)s->V;
+    k_fill<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, 3L * s->V, 0.0f);
+    k_fill<<<nblk(s->T, 256), 256, 0, st>>>(dA, s->T, 0.0f);
+    k_fill<<<1, 64, 0, st>>>(camacc, 12, 0.0f);
+    uint32_t terms = a.terms;
+    unsigned long long* cbase = a.counters;
+    if ((terms & DR_TERM_PRIMARY) && s->E > 0) {
+        EvScope ev(s, 1, st);
+        a.counters = cbase ? cbase + 8 : nullptr;
+        k_primary<<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, s->pe.as<PEdge>(), s->pcdf.as<double>(), d_image, dV, camacc);
+    }
+    if (o.max_depth >= 1) {
+        TreeView tv;
+        tv.nodes = s->etree.as<ETNode>();
+        tv.valid = (s->n1 + s->n2) > 0 && (terms & DR_TERM_SECONDARY) && s->tree_valid;
+        tv.cam = cam.c;
+        EvScope ev(s, 2, st);
+        a.counters = cbase ? cbase + 16 : nullptr;
+        if (o.max_depth <= 1)
+            k_backward<1><<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc);
+        else if (o.max_depth <= 3)
+            k_backward<3><<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc);
+        else
+            k_backward<6><<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc);
+    }
+    if (d_camera)
+        k_cam_finalize<<<1, 1, 0, st>>>(cam, camacc, d_camera);
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+}  // namespace dr
