@@ -518,8 +518,10 @@ struct View {
     bool tie = false;
 };
 
-bool clip_segment(double A[2], double B[2], double x0, double y0, double x1, double y1, double out0[2], double out1[2]) {
-    double t0 = 0, t1 = 1, dx = B[0] - A[0], dy = B[1] - A[1];
+// Window clip of the screen segment A + l (B - A), l in [t0, t1].
+bool clip_segment(double A[2], double B[2], double t0, double t1, double x0, double y0, double x1, double y1,
+                  double out0[2], double out1[2]) {
+    double dx = B[0] - A[0], dy = B[1] - A[1];
     double p[4] = {-dx, dx, -dy, dy}, qv[4] = {A[0] - x0, x1 - A[0], A[1] - y0, y1 - A[1]};
     for (int i = 0; i < 4; ++i) {
         if (p[i] == 0) {
@@ -588,14 +590,19 @@ void build_view(const Scn& s, const orc_camera& oc, View& vw) {
         if (disc_from(s, e, c, &vw.tie)) {
             V3d a, b;
             if (near_clip(vw.cam, s.p(e.va), s.p(e.vb), a, b)) {
+                // the visible (near-clipped) segment, as a parameter range on the
+                // line through the projections of the alpha points
                 project(vw.cam, a, p.A[0], p.A[1]);
                 project(vw.cam, b, p.B[0], p.B[1]);
-                if (clip_segment(p.A, p.B, vw.x0, vw.y0, vw.x1, vw.y1, p.Ac, p.Bc))
-                    p.len = std::hypot(p.Bc[0] - p.Ac[0], p.Bc[1] - p.Ac[1]);
                 V3d aa, ba;
                 alpha_points(vw.cam, s.p(e.va), s.p(e.vb), aa, ba);
                 project(vw.cam, aa, p.Aa[0], p.Aa[1]);
                 project(vw.cam, ba, p.Ba[0], p.Ba[1]);
+                double dx = p.Ba[0] - p.Aa[0], dy = p.Ba[1] - p.Aa[1], dd = dx * dx + dy * dy;
+                double l0 = ((p.A[0] - p.Aa[0]) * dx + (p.A[1] - p.Aa[1]) * dy) / dd;
+                double l1 = ((p.B[0] - p.Aa[0]) * dx + (p.B[1] - p.Aa[1]) * dy) / dd;
+                if (dd > 0 && clip_segment(p.Aa, p.Ba, l0, l1, vw.x0, vw.y0, vw.x1, vw.y1, p.Ac, p.Bc))
+                    p.len = std::hypot(p.Bc[0] - p.Ac[0], p.Bc[1] - p.Ac[1]);
             }
         }
         acc += p.len;

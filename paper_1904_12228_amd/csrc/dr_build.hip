@@ -318,36 +318,25 @@ Cam make_cam(const drCamera& c) {
 // ---------------------------------------------------------------------------
 // primary edge table
 // ---------------------------------------------------------------------------
-__device__ inline void project(const Cam& k, v3 P, float& sx, float& sy) {
-    v3 q = P - k.c;
-    float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);
-    sx = (1.0f + xc / (z * (k.asp * k.th))) * (k.W * 0.5f);
-    sy = (1.0f - yc / (z * k.th)) * (k.H * 0.5f);
-}
-
-__device__ inline bool silhouette_from(const SceneView& s, int4 e, v3 q) {
-    v3 pa = ld3(s.P, e.x);
-    v3 w = q - pa;
-    TriGeom g0 = tri_geom(s, e.z), g1 = tri_geom(s, e.w);
-    float s0 = dot(cross(g0.e1, g0.e2), w), s1 = dot(cross(g1.e1, g1.e2), w);
-    return (s0 > 0.0f) != (s1 > 0.0f);
-}
-
-__device__ inline bool clip_segment(const float A[2], const float B[2], float x0, float y0, float x1, float y1,
-                                    float o0[2], float o1[2]) {
-    float t0 = 0.0f, t1 = 1.0f, dx = B[0] - A[0], dy = B[1] - A[1];
+// Clips the screen segment P(l) = A + l (B - A), l in [l0, l1], to the window
+// (Liang-Barsky in the parameter). Points are formed from A, a point of
+// moderate screen coordinates, so their FP32 error stays at the ulp of the
+// window coordinates even when the segment extends far off screen.
+__device__ inline bool clip_param(const float A[2], const float B[2], float l0, float l1, float x0, float y0, float x1,
+                                  float y1, float o0[2], float o1[2]) {
+    float dx = B[0] - A[0], dy = B[1] - A[1];
     float p[4] = {-dx, dx, -dy, dy}, q[4] = {A[0] - x0, x1 - A[0], A[1] - y0, y1 - A[1]};
     for (int i = 0; i < 4; ++i) {
         if (p[i] == 0.0f) {
             if (q[i] < 0.0f) return false;
         } else {
             float r = q[i] / p[i];
-            if (p[i] < 0.0f) { if (r > t1) return false; if (r > t0) t0 = r; }
-            else { if (r < t0) return false; if (r < t1) t1 = r; }
+            if (p[i] < 0.0f) { if (r > l1) return false; if (r > l0) l0 = r; }
+            else { if (r < l0) return false; if (r < l1) l1 = r; }
         }
     }
-    o0[0] = A[0] + t0 * dx; o0[1] = A[1] + t0 * dy;
-    o1[0] = A[0] + t1 * dx; o1[1] = A[1] + t1 * dy;
+    o0[0] = A[0] + l0 * dx; o0[1] = A[1] + l0 * dy;
+    o1[0] = A[0] + l1 * dx; o1[1] = A[1] + l1 * dy;
     return true;
 }
 
@@ -363,12 +352,26 @@ __global__ void k_pedge(SceneView s, Cam k, PEdge* __restrict__ pe, double* __re
         v3 a = ld3(s.P, e.x), b = ld3(s.P, e.y);
         float za = dot(a - k.c, k.f), zb = dot(b - k.c, k.f);
         if (!(za < k.nearc && zb < k.nearc)) {
-            v3 ac = a, bc = b;
-            if (za < k.nearc) ac = a + (b - a) * ((k.nearc - za) / (zb - za));
-            if (zb < k.nearc) bc = b + (a - b) * ((k.nearc - zb) / (za - zb));
-            project(k, ac, r.A[0], r.A[1]);
-            project(k, bc, r.B[0], r.B[1]);
-            if (clip_segment(r.A, r.B, (float)k.x0, (float)k.y0, (float)k.x1, (float)k.y1, r.Ac, r.Bc))
+            // the line through the projections of the alpha points (A, B) ...
+            v3 aa = za < k.nearc ? alpha_point(k, a, b, za, zb) : a;
+            v3 ba = zb < k.nearc ? alpha_point(k, b, a, zb, za) : b;
+            project(k, aa, r.A[0], r.A[1]);
+            project(k, ba, r.B[0], r.B[1]);
+            // ... restricted to the part in front of the near plane
+            float dx = r.B[0] - r.A[0], dy = r.B[1] - r.A[1];
+            float dd = dx * dx + dy * dy;
+            float l0 = 0.0f, l1 = 1.0f;
+            if (za < k.nearc) {
+                float px, py;
+                project(k, a + (b - a) * ((k.nearc - za) / (zb - za)), px, py);
+                l0 = ((px - r.A[0]) * dx + (py - r.A[1]) * dy) / dd;
+            }
+            if (zb < k.nearc) {
+                float px, py;
+                project(k, b + (a - b) * ((k.nearc - zb) / (za - zb)), px, py);
+                l1 = ((px - r.A[0]) * dx + (py - r.A[1]) * dy) / dd;
+            }
+            if (dd > 0.0f && clip_param(r.A, r.B, l0, l1, (float)k.x0, (float)k.y0, (float)k.x1, (float)k.y1, r.Ac, r.Bc))
                 len = sqrtf((r.Bc[0] - r.Ac[0]) * (r.Bc[0] - r.Ac[0]) + (r.Bc[1] - r.Ac[1]) * (r.Bc[1] - r.Ac[1]));
         }
     }

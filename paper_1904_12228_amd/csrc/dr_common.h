@@ -129,7 +129,9 @@ __device__ inline v3 cam_dir(const Cam& k, float sx, float sy) {
     return k.f + k.r * (nx * k.asp * k.th) + k.u * (ny * k.th);
 }
 
-struct PEdge { float A[2], B[2], Ac[2], Bc[2]; };   // projected (near-clipped) and screen-clipped
+// Primary edge record: A, B = projections of the two points defining the edge
+// equation; Ac, Bc = the sampled segment (visible part, clipped to the window).
+struct PEdge { float A[2], B[2], Ac[2], Bc[2]; };
 
 // Edge hierarchy node: both children's data, so one fetch evaluates a split.
 struct ETChild {

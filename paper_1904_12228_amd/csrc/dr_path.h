@@ -130,4 +130,32 @@ __device__ inline float radiance(const SceneView& s, const Rng& rng, int base, v
     return L;
 }
 
+// Projection to pixels (y down).
+__device__ inline void project(const Cam& k, v3 P, float& sx, float& sy) {
+    v3 q = P - k.c;
+    float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);
+    sx = (1.0f + xc / (z * (k.asp * k.th))) * (k.W * 0.5f);
+    sy = (1.0f - yc / (z * k.th)) * (k.H * 0.5f);
+}
+
+// Points defining the edge equation alpha (eq. edge_equation): the endpoints,
+// except that an endpoint behind the near plane is replaced by the edge point
+// at depth zd = max(near, half the other endpoint's depth). Any two points of
+// the edge in front of the camera give the same projected line, hence the same
+// boundary term; this choice keeps the projection well conditioned (a point at
+// depth `near` projects far off screen with a 1/near^2 Jacobian).
+__device__ inline v3 alpha_point(const Cam& k, v3 a, v3 b, float za, float zb) {
+    float zd = fmaxf(k.nearc, 0.5f * zb);
+    return a + (b - a) * ((zd - za) / (zb - za));
+}
+
+// An edge is a silhouette from q when its two faces lie on opposite sides of q.
+__device__ inline bool silhouette_from(const SceneView& s, int4 e, v3 q) {
+    v3 pa = ld3(s.P, e.x);
+    v3 w = q - pa;
+    TriGeom g0 = tri_geom(s, e.z), g1 = tri_geom(s, e.w);
+    float s0 = dot(cross(g0.e1, g0.e2), w), s1 = dot(cross(g1.e1, g1.e2), w);
+    return (s0 > 0.0f) != (s1 > 0.0f);
+}
+
 }  // namespace dr

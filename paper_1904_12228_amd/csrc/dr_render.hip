@@ -143,14 +143,7 @@ __device__ inline void atomic_add3(float* p, int i, v3 v) {
     if (v.z != 0.0f) atomicAdd(&p[3 * i + 2], v.z);
 }
 
-// Projection to pixels and its adjoint.
-__device__ inline void project(const Cam& k, v3 P, float& sx, float& sy) {
-    v3 q = P - k.c;
-    float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);
-    sx = (1.0f + xc / (z * (k.asp * k.th))) * (k.W * 0.5f);
-    sy = (1.0f - yc / (z * k.th)) * (k.H * 0.5f);
-}
-
+// Adjoint of the projection to pixels.
 __device__ inline v3 project_adj(const Cam& k, v3 P, float gsx, float gsy, CamAcc& ca) {
     v3 q = P - k.c;
     float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);
@@ -164,16 +157,6 @@ __device__ inline v3 project_adj(const Cam& k, v3 P, float gsx, float gsy, CamAc
     ca.u += q * gyc;
     ca.c -= gq;
     return gq;
-}
-
-// Points defining the edge equation alpha (eq. edge_equation): the endpoints,
-// except that an endpoint behind the near plane is replaced by the edge point
-// at depth zd = max(near, half the other endpoint's depth). Any two points of
-// the edge in front of the camera give the same projected line, hence the same
-// boundary term; this choice keeps the projection well conditioned.
-__device__ inline v3 alpha_point(const Cam& k, v3 a, v3 b, float za, float zb) {
-    float zd = fmaxf(k.nearc, 0.5f * zb);
-    return a + (b - a) * ((zd - za) / (zb - za));
 }
 
 // Adjoint of a* = a + (b - a) s, s = (zd - za)/(zb - za), zd = max(near, zb/2).
@@ -430,14 +413,6 @@ __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rn
         node = ref;
         ++level;
     }
-}
-
-__device__ inline bool silhouette_from(const SceneView& s, int4 e, v3 q) {
-    v3 pa = ld3(s.P, e.x);
-    v3 w = q - pa;
-    TriGeom g0 = tri_geom(s, e.z), g1 = tri_geom(s, e.w);
-    float s0 = dot(cross(g0.e1, g0.e2), w), s1 = dot(cross(g1.e1, g1.e2), w);
-    return (s0 > 0.0f) != (s1 > 0.0f);
 }
 
 // ---------------------------------------------------------------------------
