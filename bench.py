@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="first run one plain device copy of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -98,6 +100,14 @@ def main():
     import torch
 
     from paper_1904_12228_amd import api, scenegen
+
+    if args.pmc_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)              # reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
 
     cfg = scenegen.CONFIGS[args.workload]()
     cam = cfg.camera

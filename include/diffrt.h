@@ -117,6 +117,13 @@ drStatus drRenderBackward(drScene scene, const drCamera* camera, const drRenderO
                           const float* d_image, float* d_vertices, float* d_albedo, float* d_camera,
                           hipStream_t stream);
 
+/* One Adam step (Kingma and Ba, with bias correction) on n FP32 parameters,
+ * all device arrays of length n: x -= lr * mhat / (sqrt(vhat) + eps), with
+ * m, v updated in place; `step` counts from 1. Used by inverse-rendering
+ * loops (the thesis optimises with Adam, Ch. 5 Results). */
+drStatus drAdamStep(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1,
+                    float beta2, float eps, int64_t step, hipStream_t stream);
+
 /* Measurement support (not needed for rendering). With `events` on, every
  * forward, primary-edge and path-backward kernel launch is bracketed by HIP
  * events on the stream it runs on; with `counters` on, the kernels also count

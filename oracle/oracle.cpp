@@ -1261,7 +1261,9 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             Stream rp{(uint32_t)m, o.view_id, TAG_PEDGE, C.k0, C.k1};
             double b0[4];
             rp.block(0, b0);
-            int ei = cdf_pick(vw.pcdf, b0[0], U);
+            // stratified edge choice: unit m draws its uniform in [m/M, (m+1)/M)
+            double us = ((double)m + b0[0]) / (double)C.M;
+            int ei = cdf_pick(vw.pcdf, us, U);
             const PEdge& pe = vw.pe[ei];
             double t = b0[1];
             double x = pe.Ac[0] + (pe.Bc[0] - pe.Ac[0]) * t, y = pe.Ac[1] + (pe.Bc[1] - pe.Ac[1]) * t;

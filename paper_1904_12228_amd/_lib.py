@@ -19,7 +19,8 @@ DR_TERM_ALL = 7
 
 # every entry point declared in include/diffrt.h
 EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneGetInfo", "drRender", "drRenderBackward",
-           "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy", "drGetErrorString"]
+           "drAdamStep", "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy",
+           "drGetErrorString"]
 
 
 class SceneDesc(C.Structure):
@@ -71,6 +72,7 @@ def load():
         "drSceneGetInfo": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "drRender": [vp, C.POINTER(Camera), C.POINTER(RenderOptions), vp, vp],
         "drRenderBackward": [vp, C.POINTER(Camera), C.POINTER(RenderOptions), vp, vp, vp, vp, vp],
+        "drAdamStep": [vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int64, vp],
         "drSetProfiling": [vp, i32, i32],
         "drGetProfile": [vp, C.POINTER(Profile), i32],
         "drGetLastDeviceError": [vp],

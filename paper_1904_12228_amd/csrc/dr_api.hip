@@ -37,6 +37,7 @@ SceneView drScene_t::view() const {
     v.two_sided = two_sided;
     v.background = background;
     v.err = err.as<int>();
+    v.stk_cap = kStackDepth;
     return v;
 }
 

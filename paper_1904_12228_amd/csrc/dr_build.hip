@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "dr_host.h"
 #include "dr_path.h"
@@ -246,6 +247,15 @@ __global__ void k_bvh_refit(const float* __restrict__ P, const int* __restrict__
     }
 }
 
+// Internal nodes above each leaf (the traversal stack never holds more).
+__global__ void k_tree_depth(const int* __restrict__ parent, int n, float* __restrict__ out) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    int dep = 0;
+    for (int q = parent[n - 1 + g]; q >= 0 && dep <= n; q = parent[q >> 1]) ++dep;
+    atomicMax(reinterpret_cast<int*>(out), dep);
+}
+
 drStatus build_scene_static(drScene_t* s, hipStream_t st) {
     const int BS = 256;
     int T = s->T, V = s->V;
@@ -273,14 +283,19 @@ drStatus build_scene_static(drScene_t* s, hipStream_t st) {
                                                      s->ids.as<int>());
         k_bvh_refit<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->ids_s.as<int>(),
                                                   s->parent.as<int>(), s->bvh.as<BvhNode>(), s->ids.as<int>());
+        DR_CHECK(hipMemsetAsync(s->scal.as<float>() + 13, 0, sizeof(int), st));
+        k_tree_depth<<<blocks(T, BS), BS, 0, st>>>(s->parent.as<int>(), T, s->scal.as<float>() + 13);
     }
-    float sc[13];
+    float sc[14];
     DR_CHECK(hipMemcpyAsync(sc, s->scal.p, sizeof(sc), hipMemcpyDeviceToHost, st));
     DR_CHECK(hipStreamSynchronize(st));
     float dx = sc[9] - sc[6], dy = sc[10] - sc[7], dz = sc[11] - sc[8];
     s->diag = std::sqrt(dx * dx + dy * dy + dz * dz);
     s->tmin = kTminRel * s->diag;
     s->atot = s->L > 0 ? sc[12] : 0.0f;
+    int dep = 0;
+    if (T > 1) std::memcpy(&dep, &sc[13], sizeof(int));
+    s->bvh_depth = dep;
     return DR_SUCCESS;
 }
 

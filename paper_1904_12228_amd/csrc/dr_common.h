@@ -20,7 +20,7 @@ constexpr float kHorizon = 1e-5f;     // edge points this * diagonal below/at th
 constexpr float kVsphereMargin = 1e-5f;  // v-sphere pruning only beyond this relative margin
 constexpr float kPi = 3.14159265358979323846f;
 constexpr int kMaxDepth = 6;
-constexpr int kStackDepth = 64;       // BVH traversal stack entries per lane
+constexpr int kStackDepth = 64;       // largest BVH traversal stack (entries per lane)
 constexpr int kMaxLevels = 64;        // edge-tree descent levels (16 Philox blocks x 4)
 constexpr int kSideBlockBase = 32;    // Philox block base of secondary side paths
 constexpr uint32_t kTagCam = 0, kTagPedge = 1, kTagSedge = 1;  // SEDGE_k = 1 + k
@@ -115,6 +115,7 @@ struct SceneView {
     int two_sided;
     float background;
     int* err;                // sticky device error flags
+    int stk_cap;             // traversal stack entries per lane in this launch (>= BVH depth)
 };
 
 struct Cam {
@@ -157,6 +158,15 @@ enum : int { kErrStack = 1, kErrTreeDepth = 2 };
 // nodes, atomics, rays.
 struct Work {
     uint32_t nodes = 0, tris = 0, tnodes = 0, atom = 0, rays = 0;
+    __device__ void ray(uint32_t n, uint32_t t) { nodes += n; tris += t; rays += 1; }
+    __device__ void tree() { ++tnodes; }
+    __device__ void atomics(uint32_t n) { atom += n; }
+};
+// The same interface with no state: the production kernels count nothing.
+struct NoWork {
+    __device__ void ray(uint32_t, uint32_t) {}
+    __device__ void tree() {}
+    __device__ void atomics(uint32_t) {}
 };
 
 }  // namespace dr

@@ -52,6 +52,7 @@ struct drScene_t {
     int two_sided = 0;
     float background = 0.0f;
     float diag = 0.0f, tmin = 0.0f, atot = 0.0f;
+    int bvh_depth = 0;               // internal nodes on the longest root-to-leaf path
     uint64_t version = 0;            // bumps on every vertex update
     // scene data
     dr::Buf P, I, N, alb, emi, tri, bvh, edges, ekind, lights, lcdf, scal, err;

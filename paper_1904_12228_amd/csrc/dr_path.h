@@ -45,8 +45,17 @@ __device__ inline float emitted(const SceneView& s, int id, bool front) {
     return (front || s.two_sided) ? e : 0.0f;
 }
 
+// first index with cdf[i] > u
+__device__ inline int pick_cdf_d(const double* cdf, int n, double ud) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cdf[mid] > ud) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 __device__ inline int pick_cdf(const double* cdf, int n, float u) {
-    // first index with cdf[i] > u
     int lo = 0, hi = n - 1;
     double ud = (double)u;
     while (lo < hi) {
@@ -97,8 +106,9 @@ __device__ inline v3 cosine_dir(v3 n, float u0, float u1) {
 // Radiance arriving along a ray: emission at the first hit, then NEE at path
 // vertices 1..budget with cosine continuation between them. camera: misses
 // return the background and t_min is the near clip.
+template <class W>
 __device__ inline float radiance(const SceneView& s, const Rng& rng, int base, v3 o, v3 d, float tmin, bool camera,
-                                 int budget, int* stk, int stride, Work* wk = nullptr) {
+                                 int budget, int* stk, int stride, W& wk) {
     Hit h = trace_closest(s, o, d, tmin, 3.0e38f, stk, stride, wk);
     if (h.tri < 0) return camera ? s.background : 0.0f;
     int tri = h.tri;

@@ -12,6 +12,7 @@
 // direction-space edges at each vertex (eq. dirac_3d_edge in the solid-angle
 // measure; its endpoint terms equal the thesis's area form exactly).
 #include <cstdlib>
+#include <type_traits>
 
 #include "dr_host.h"
 #include "dr_path.h"
@@ -40,6 +41,8 @@ __device__ inline void unit_pixel(const Cam& k, const RenderArgs& a, int m, int&
     sid = ((uint32_t)py * (uint32_t)k.W + (uint32_t)px) * (uint32_t)a.spp + (uint32_t)smp;
 }
 
+__device__ inline void flush_work(const NoWork&, unsigned long long*) {}
+
 __device__ inline void flush_work(const Work& w, unsigned long long* c) {
     if (!c) return;
     uint32_t v[5] = {w.nodes, w.tris, w.tnodes, w.atom, w.rays};
@@ -53,15 +56,15 @@ __device__ inline void flush_work(const Work& w, unsigned long long* c) {
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
+template <int STK, bool CNT>
 __global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a, float* __restrict__ image, int reduce) {
-    __shared__ int stk[kStackDepth * BS];
+    __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
     int m = blockIdx.x * BS + lane;
     float L = 0.0f;
     int pix = 0;
-    Work wk;
-    Work* pw = a.counters ? &wk : nullptr;
+    typename std::conditional<CNT, Work, NoWork>::type wk;
     if (m < a.M) {
         int px, py;
         uint32_t sid;
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a
             Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
             float4 j = rc.block(0);
             v3 d = cam_dir(k, px + j.x, py + j.y);
-            Hit h = trace_closest(s, k.c, d, k.nearc, 3.0e38f, my, BS, pw);
+            Hit h = trace_closest(s, k.c, d, k.nearc, 3.0e38f, my, BS, wk);
             if (h.tri < 0) {
                 L = s.background;
             } else {
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a
                     float rho = s.alb[tri];
                     if (rho == 0.0f) break;
                     NeeSample q = nee_sample(s, rc.block(2 * kk - 1), x, ns);
-                    if (q.K > 0.0f && !trace_any(s, x, q.w, s.tmin, q.r * (1.0f - kShadowEnd), my, BS, pw)) {
+                    if (q.K > 0.0f && !trace_any(s, x, q.w, s.tmin, q.r * (1.0f - kShadowEnd), my, BS, wk)) {
                         L += beta * rho * dot(ns, q.w) * q.K;
                         vis |= (uint8_t)(1u << (kk - 1));
                     }
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a
                     float4 ub = rc.block(2 * kk);
                     v3 w = cosine_dir(ns, ub.x, ub.y);
                     if (dot(ns, w) <= 0.0f) break;
-                    Hit h2 = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, pw);
+                    Hit h2 = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, wk);
                     if (h2.tri < 0) break;
                     beta *= rho;
                     tri = h2.tri;
@@ -236,6 +239,42 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+__device__ inline float wave_sum_all(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, BS);
+    return v;
+}
+
+// Gradient scatter with in-wave pre-reduction. Lanes holding the same key
+// (an edge or a triangle) are summed with cross-lane shuffles and one lane
+// issues the atomics, which removes same-address atomic contention when the
+// lanes of a wave work on the same primitive (all samples of a pixel, or the
+// stratified primary edge samples). After `max_groups` distinct keys the
+// remaining lanes add their values directly. Must be called by all lanes.
+template <int N, class Dest>
+__device__ inline void scatter_grouped(bool valid, int key, const float (&vals)[N], int max_groups, Dest dest) {
+    const int lane = threadIdx.x;
+    unsigned long long active = __ballot(valid);
+    for (int it = 0; active; ++it) {
+        if (it == max_groups) {
+            if ((active >> lane) & 1ull)
+#pragma unroll
+                for (int i = 0; i < N; ++i)
+                    if (vals[i] != 0.0f) atomicAdd(dest(key, i), vals[i]);
+            break;
+        }
+        int leader = __ffsll(active) - 1;
+        int lkey = __shfl(key, leader, BS);
+        bool mine = ((active >> lane) & 1ull) && key == lkey;
+        unsigned long long grp = __ballot(mine);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float v = wave_sum_all(mine ? vals[i] : 0.0f);
+            if (lane == leader && v != 0.0f) atomicAdd(dest(lkey, i), v);
+        }
+        active &= ~grp;
+    }
+}
+
 __device__ inline void flush_cam(const CamAcc& ca, float* camacc) {
     float v[12] = {ca.f.x, ca.f.y, ca.f.z, ca.r.x, ca.r.y, ca.r.z, ca.u.x, ca.u.y, ca.u.z, ca.c.x, ca.c.y, ca.c.z};
     for (int i = 0; i < 12; ++i) {
@@ -247,21 +286,26 @@ __device__ inline void flush_cam(const CamAcc& ca, float* camacc) {
 // ---------------------------------------------------------------------------
 // primary edge samples (eq. mc): one per unit
 // ---------------------------------------------------------------------------
+template <int STK, bool CNT>
 __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
                                                 const double* __restrict__ cdf, const float* __restrict__ d_image,
                                                 float* __restrict__ dV, float* __restrict__ camacc) {
-    __shared__ int stk[kStackDepth * BS];
+    __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
     int m = blockIdx.x * BS + lane;
     CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    Work wk;
-    Work* pw = a.counters ? &wk : nullptr;
+    typename std::conditional<CNT, Work, NoWork>::type wk;
     double total = cdf[s.E];
+    bool have = false;
+    int key = -1;
+    float gv[6] = {0, 0, 0, 0, 0, 0};
     if (m < a.M && (!a.mask || a.mask[m]) && total > 0.0) {
         Rng rp{(uint32_t)m, a.view, kTagPedge, a.k0, a.k1};
         float4 b0 = rp.block(0);
-        int ei = pick_cdf(cdf, s.E, b0.x);
+        // stratified edge choice: unit m draws its uniform in [m/M, (m+1)/M), so
+        // the lanes of a wave take neighbouring edges in CDF order
+        int ei = pick_cdf_d(cdf, s.E, ((double)m + (double)b0.x) / (double)a.M);
         PEdge p = pe[ei];
         float t = b0.y;
         float x = p.Ac[0] + (p.Bc[0] - p.Ac[0]) * t, y = p.Ac[1] + (p.Bc[1] - p.Ac[1]) * t;
@@ -276,8 +320,8 @@ __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a
         float dx = Ax - Bx, dy = Ay - By;
         float nl = sqrtf(dx * dx + dy * dy);
         float nx = (Ay - By) / nl, ny = (Bx - Ax) / nl;
-        float fu = radiance(s, rp, 0, k.c, cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), k.nearc, true, a.depth, my, BS, pw);
-        float fl = radiance(s, rp, 0, k.c, cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny), k.nearc, true, a.depth, my, BS, pw);
+        float fu = radiance(s, rp, 0, k.c, cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), k.nearc, true, a.depth, my, BS, wk);
+        float fl = radiance(s, rp, 0, k.c, cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny), k.nearc, true, a.depth, my, BS, wk);
         if (m == a.debug_unit)
             printf("punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g n %.9g %.9g fu %.9g fl %.9g total %.9g\n", m, ei, x,
                    y, Ax, Ay, Bx, By, nx, ny, fu, fl, total);
@@ -295,11 +339,17 @@ __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a
             else ga += gac;
             if (zb < k.nearc) nearclip_adj(k, vb, va, gbc, gb, ga, ca);
             else gb += gbc;
-            atomic_add3(dV, e.x, ga);
-            atomic_add3(dV, e.y, gb);
-            wk.atom += 6;
+            have = true;
+            key = ei;
+            gv[0] = ga.x; gv[1] = ga.y; gv[2] = ga.z;
+            gv[3] = gb.x; gv[4] = gb.y; gv[5] = gb.z;
+            wk.atomics(6);
         }
     }
+    scatter_grouped(have, key, gv, 4, [&](int ek, int i) {
+        int4 e = s.edges[ek];
+        return &dV[3 * (i < 3 ? e.x : e.y) + (i % 3)];
+    });
     flush_work(wk, a.counters);
     flush_cam(ca, camacc);
 }
@@ -372,8 +422,9 @@ __device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, 
     return c.len * b / len(ctr - q.p);
 }
 
-__device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rng& rk, float u_root, float& pdf,
-                                  bool dbg = false, Work* wk = nullptr) {
+template <class W>
+__device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rng& rk, float u_root, float& pdf, W& wk,
+                                  bool dbg = false) {
     const ETNode* nodes = tv.nodes;
     int node = 0;
     float plo[3], phi[3];
@@ -389,7 +440,7 @@ __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rn
     float4 ub = make_float4(0, 0, 0, 0);
     while (true) {
         const ETNode& N = nodes[node];
-        if (wk) wk->tnodes++;
+        wk.tree();
         int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
         float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
         float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
@@ -418,16 +469,18 @@ __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rn
 // ---------------------------------------------------------------------------
 // backward over paths: secondary edges at every vertex + interior adjoint
 // ---------------------------------------------------------------------------
-template <int MAXD>
+template <int MAXD, int STK, bool CNT>
 __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs a, TreeView tv, const float* __restrict__ d_image,
                                                  float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc) {
-    __shared__ int stk[kStackDepth * BS];
+    __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
     int m = blockIdx.x * BS + lane;
     CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    Work wk;
-    Work* pw = a.counters ? &wk : nullptr;
+    typename std::conditional<CNT, Work, NoWork>::type wk;
+    bool have0 = false;          // vertex-1 triangle gradients, scattered per wave group
+    int key0 = -1;
+    float g0[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (m < a.M && (!a.mask || a.mask[m]) && a.depth >= 1 && a.ck_tri[m] >= 0) {
         int pix, px, py;
         uint32_t sid;
@@ -440,9 +493,11 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
         v3 d0 = k.f + k.r * (ndx * k.asp * k.th) + k.u * (ndy * k.th);
         uint8_t vis = a.ck_vis[m];
         // ---- rebuild the path's vertices
+        // per vertex: the ray reaching vertex k starts at vertex k-1 (camera for
+        // k = 0) along wc[k-1] (camera direction d0 for k = 0)
         int tri[MAXD];
-        v3 org[MAXD], dir[MAXD], xs[MAXD], ns[MAXD], wy[MAXD], wc[MAXD];
-        float sg[MAXD], rho[MAXD], beta[MAXD], K[MAXD], cc[MAXD];
+        v3 xs[MAXD], ns[MAXD], wc[MAXD];
+        float sg[MAXD], rho[MAXD], beta[MAXD], cc[MAXD];
         int nv = 0;
         {
             int t = a.ck_tri[m];
@@ -457,10 +512,7 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                 v3 n = shading_normal(s, t, g, x) * sgn;
                 float r = s.alb[t];
                 if (r == 0.0f) break;
-                tri[kk] = t; org[kk] = o; dir[kk] = d; xs[kk] = x; ns[kk] = n; sg[kk] = sgn; rho[kk] = r; beta[kk] = b;
-                NeeSample q = nee_sample(s, rc.block(2 * kk + 1), x, n);
-                K[kk] = ((vis >> kk) & 1) ? q.K : 0.0f;
-                wy[kk] = q.w;
+                tri[kk] = t; xs[kk] = x; ns[kk] = n; sg[kk] = sgn; rho[kk] = r; beta[kk] = b;
                 cc[kk] = 0.0f;
                 wc[kk] = {0, 0, 0};
                 nv = kk + 1;
@@ -477,7 +529,7 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                     const float* cx = a.ck_x + 3 * ((size_t)a.M + m);
                     x2 = {cx[0], cx[1], cx[2]};
                 } else {
-                    Hit h = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, pw);
+                    Hit h = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, wk);
                     if (h.tri < 0) break;
                     t2 = h.tri;
                     x2 = hit_point(tri_geom(s, t2), x, w);
@@ -503,7 +555,7 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                 TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
                 float pdf;
                 bool dbg = m == a.debug_unit;
-                int ei = tree_sample(tv, q, rk, b0.x, pdf, dbg, pw);
+                int ei = tree_sample(tv, q, rk, b0.x, pdf, wk, dbg);
                 if (ei < 0) continue;
                 int4 e = s.edges[ei];
                 if (e.z == tri[kk] || e.w == tri[kk]) continue;
@@ -520,8 +572,8 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                 v3 wh = w * (1.0f / wl);
                 v3 wp = nrm(wh + nh * kEps3), wm = nrm(wh - nh * kEps3);
                 int rem = a.depth - (kk + 1);
-                float Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, pw);
-                float Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, pw);
+                float Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, wk);
+                float Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, wk);
                 // the cosine is continuous across the edge; only the radiance jumps
                 float cosw = dot(n, wh);
                 float Fp = rho[kk] / kPi * cosw * Lp;
@@ -535,7 +587,7 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                            m, kk + 1, tri[kk], p.x, p.y, p.z, n.x, n.y, n.z, ei, pdf, b0.y, Lp, Lm, cosw, Wk, wgt);
                 atomic_add3(dV, e.x, cross(v1p, wh) * wgt);
                 atomic_add3(dV, e.y, cross(wh, v0p) * wgt);
-                wk.atom += 6;
+                wk.atomics(6);
                 xbar[kk] += (cross(wh, v1p) + cross(v0p, wh)) * wgt;
             }
         }
@@ -549,17 +601,22 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
             if (kk >= nv) continue;
             int t = tri[kk];
             TriGeom g = tri_geom(s, t);
-            float nee_cos = dot(ns[kk], wy[kk]);
-            float Nk = rho[kk] * nee_cos * K[kk];
+            // NEE of this vertex, recomputed from its random numbers; the
+            // visibility comes from the forward pass
+            NeeSample q = nee_sample(s, rc.block(2 * kk + 1), xs[kk], ns[kk]);
+            float Kk = ((vis >> kk) & 1) ? q.K : 0.0f;
+            float nee_cos = dot(ns[kk], q.w);
+            float Nk = rho[kk] * nee_cos * Kk;
             bool cont = cc[kk] > 0.0f;
             float Ab = cont ? Aft : 0.0f;
             v3 gns = {0, 0, 0};
             if (interior) {
                 float gN = W0 * beta[kk];
                 float gw = cont ? W0 * beta[kk] * Ab : 0.0f;
-                float grho = gN * nee_cos * K[kk] + gw;
-                if (grho != 0.0f) atomicAdd(&dA[t], grho);
-                gns = wy[kk] * (gN * rho[kk] * K[kk]);
+                float grho = gN * nee_cos * Kk + gw;
+                if (kk == 0) g0[9] = grho;
+                else if (grho != 0.0f) atomicAdd(&dA[t], grho);
+                gns = q.w * (gN * rho[kk] * Kk);
                 if (cont) gns += wc[kk] * (gw * rho[kk] / cc[kk]);
             }
             v3 gx = xbar[kk] + carry;
@@ -567,12 +624,22 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
             if (gns.x != 0.0f || gns.y != 0.0f || gns.z != 0.0f)
                 shading_normal_adj(s, t, g, xs[kk], gns * sg[kk], gx, gp0, gp1, gp2);
             v3 go = {0, 0, 0}, gd = {0, 0, 0};
-            ray_plane_adj(g, org[kk], dir[kk], gx, go, gd, gp0, gp1, gp2);
-            int i0 = s.I[3 * t], i1 = s.I[3 * t + 1], i2 = s.I[3 * t + 2];
-            atomic_add3(dV, i0, gp0);
-            atomic_add3(dV, i1, gp1);
-            atomic_add3(dV, i2, gp2);
-            wk.atom += 10;
+            v3 org = kk == 0 ? k.c : xs[kk == 0 ? 0 : kk - 1];
+            v3 dir = kk == 0 ? d0 : wc[kk == 0 ? 0 : kk - 1];
+            ray_plane_adj(g, org, dir, gx, go, gd, gp0, gp1, gp2);
+            if (kk == 0) {
+                have0 = true;
+                key0 = t;
+                g0[0] = gp0.x; g0[1] = gp0.y; g0[2] = gp0.z;
+                g0[3] = gp1.x; g0[4] = gp1.y; g0[5] = gp1.z;
+                g0[6] = gp2.x; g0[7] = gp2.y; g0[8] = gp2.z;
+            } else {
+                int i0 = s.I[3 * t], i1 = s.I[3 * t + 1], i2 = s.I[3 * t + 2];
+                atomic_add3(dV, i0, gp0);
+                atomic_add3(dV, i1, gp1);
+                atomic_add3(dV, i2, gp2);
+            }
+            wk.atomics(10);
             if (kk == 0) {
                 ca.c += go;
                 gd0 = gd;
@@ -586,6 +653,9 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
         ca.r += gd0 * (ndx * k.asp * k.th);
         ca.u += gd0 * (ndy * k.th);
     }
+    scatter_grouped(have0, key0, g0, 4, [&](int t, int i) {
+        return i == 9 ? &dA[t] : &dV[3 * s.I[3 * t + i / 3] + (i % 3)];
+    });
     flush_work(wk, a.counters);
     flush_cam(ca, camacc);
 }
@@ -661,15 +731,29 @@ static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions&
     return a;
 }
 
+// Traversal stack per lane: 32 entries when the BVH is at most 32 internal
+// nodes deep (then the stack can never overflow), 64 otherwise.
+static inline bool small_stack(const drScene_t* s) { return s->bvh_depth <= 32; }
+
 drStatus launch_forward(drScene_t* s, const Cam& cam, const drRenderOptions& o, float* image, hipStream_t st) {
     RenderArgs a = make_args(s, cam, o);
     SceneView sv = s->view();
+    bool sm = small_stack(s);
+    sv.stk_cap = sm ? 32 : kStackDepth;
     bool reduce = (BS % o.spp) == 0;
     long npix = (long)a.Ww * (cam.y1 - cam.y0);
     if (!reduce) k_fill<<<nblk(npix, 256), 256, 0, st>>>(image, npix, 0.0f);
     {
         EvScope ev(s, 0, st);
-        k_forward<<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, image, reduce ? 1 : 0);
+        dim3 g(nblk(a.M, BS)), b(BS);
+        int red = reduce ? 1 : 0;
+        if (a.counters) {
+            if (sm) k_forward<32, true><<<g, b, 0, st>>>(sv, cam, a, image, red);
+            else k_forward<kStackDepth, true><<<g, b, 0, st>>>(sv, cam, a, image, red);
+        } else {
+            if (sm) k_forward<32, false><<<g, b, 0, st>>>(sv, cam, a, image, red);
+            else k_forward<kStackDepth, false><<<g, b, 0, st>>>(sv, cam, a, image, red);
+        }
     }
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
@@ -678,6 +762,8 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
                          float* d_albedo, float* d_camera, hipStream_t st) {
     RenderArgs a = make_args(s, cam, o);
     SceneView sv = s->view();
+    bool sm = small_stack(s);
+    sv.stk_cap = sm ? 32 : kStackDepth;
     float* dV = d_vertices;
     float* dA = d_albedo;
     // outputs the caller did not ask for go to scratch
@@ -695,7 +781,16 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
     if ((terms & DR_TERM_PRIMARY) && s->E > 0) {
         EvScope ev(s, 1, st);
         a.counters = cbase ? cbase + 8 : nullptr;
-        k_primary<<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, s->pe.as<PEdge>(), s->pcdf.as<double>(), d_image, dV, camacc);
+        dim3 g(nblk(a.M, BS)), b(BS);
+        const PEdge* pe = s->pe.as<PEdge>();
+        const double* pc = s->pcdf.as<double>();
+        if (a.counters) {
+            if (sm) k_primary<32, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
+            else k_primary<kStackDepth, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
+        } else {
+            if (sm) k_primary<32, false><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
+            else k_primary<kStackDepth, false><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
+        }
     }
     if (o.max_depth >= 1) {
         TreeView tv;
@@ -704,12 +799,25 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         tv.cam = cam.c;
         EvScope ev(s, 2, st);
         a.counters = cbase ? cbase + 16 : nullptr;
-        if (o.max_depth <= 1)
-            k_backward<1><<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc);
-        else if (o.max_depth <= 3)
-            k_backward<3><<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc);
-        else
-            k_backward<6><<<nblk(a.M, BS), BS, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc);
+        dim3 g(nblk(a.M, BS)), b(BS);
+#define DR_BWD(D, S, C) k_backward<D, S, C><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc)
+#define DR_BWD_D(D)                                   \
+    if (a.counters) {                                 \
+        if (sm) DR_BWD(D, 32, true);                  \
+        else DR_BWD(D, kStackDepth, true);            \
+    } else {                                          \
+        if (sm) DR_BWD(D, 32, false);                 \
+        else DR_BWD(D, kStackDepth, false);           \
+    }
+        if (o.max_depth <= 1) {
+            DR_BWD_D(1)
+        } else if (o.max_depth <= 3) {
+            DR_BWD_D(3)
+        } else {
+            DR_BWD_D(6)
+        }
+#undef DR_BWD_D
+#undef DR_BWD
     }
     if (d_camera)
         k_cam_finalize<<<1, 1, 0, st>>>(cam, camacc, d_camera);

@@ -47,8 +47,8 @@ struct Hit { int tri; float t, u, v; };
 
 // Closest hit in (tmin, tmax). `stk` points at this lane's first LDS slot;
 // consecutive entries are `stride` words apart.
-__device__ inline Hit trace_closest(const SceneView& s, v3 o, v3 d, float tmin, float tmax, int* stk, int stride,
-                                   Work* wk = nullptr) {
+template <class W>
+__device__ inline Hit trace_closest(const SceneView& s, v3 o, v3 d, float tmin, float tmax, int* stk, int stride, W& wk) {
     Hit h{-1, tmax, 0.0f, 0.0f};
     uint32_t nn = 0, nt = 0;
     auto consider = [&](int id) {
@@ -58,7 +58,7 @@ __device__ inline Hit trace_closest(const SceneView& s, v3 o, v3 d, float tmin, 
     };
     if (s.T == 1) {
         consider(0);
-        if (wk) { wk->tris += nt; wk->rays += 1; }
+        wk.ray(0, nt);
         return h;
     }
     RayInv r = ray_inv(o, d);
@@ -77,7 +77,7 @@ __device__ inline Hit trace_closest(const SceneView& s, v3 o, v3 d, float tmin, 
         if (hr && rr < 0) { consider(~rr); hr = false; }
         if (hl && hr) {
             int nearc = tl <= tr ? l : rr, farc = tl <= tr ? rr : l;
-            if (sp < kStackDepth) stk[(sp++) * stride] = farc;
+            if (sp < s.stk_cap) stk[(sp++) * stride] = farc;
             else atomicOr(s.err, kErrStack);
             node = nearc;
         } else if (hl) {
@@ -89,13 +89,13 @@ __device__ inline Hit trace_closest(const SceneView& s, v3 o, v3 d, float tmin, 
             node = stk[(--sp) * stride];
         }
     }
-    if (wk) { wk->nodes += nn; wk->tris += nt; wk->rays += 1; }
+    wk.ray(nn, nt);
     return h;
 }
 
 // Any hit in (tmin, tmax).
-__device__ inline bool trace_any(const SceneView& s, v3 o, v3 d, float tmin, float tmax, int* stk, int stride,
-                                 Work* wk = nullptr) {
+template <class W>
+__device__ inline bool trace_any(const SceneView& s, v3 o, v3 d, float tmin, float tmax, int* stk, int stride, W& wk) {
     uint32_t nn = 0, nt = 0;
     auto test = [&](int id) {
         ++nt;
@@ -104,7 +104,7 @@ __device__ inline bool trace_any(const SceneView& s, v3 o, v3 d, float tmin, flo
     };
     if (s.T == 1) {
         bool r0 = test(0);
-        if (wk) { wk->tris += nt; wk->rays += 1; }
+        wk.ray(0, nt);
         return r0;
     }
     RayInv r = ray_inv(o, d);
@@ -123,7 +123,7 @@ __device__ inline bool trace_any(const SceneView& s, v3 o, v3 d, float tmin, flo
         if (hl && l < 0) { if (test(~l)) { hit = true; break; } hl = false; }
         if (hr && rr < 0) { if (test(~rr)) { hit = true; break; } hr = false; }
         if (hl && hr) {
-            if (sp < kStackDepth) stk[(sp++) * stride] = rr;
+            if (sp < s.stk_cap) stk[(sp++) * stride] = rr;
             else atomicOr(s.err, kErrStack);
             node = l;
         } else if (hl) {
@@ -135,7 +135,7 @@ __device__ inline bool trace_any(const SceneView& s, v3 o, v3 d, float tmin, flo
             node = stk[(--sp) * stride];
         }
     }
-    if (wk) { wk->nodes += nn; wk->tris += nt; wk->rays += 1; }
+    wk.ray(nn, nt);
     return hit;
 }
 
