@@ -47,14 +47,15 @@ class _Options(C.Structure):
                 ("view_id", C.c_uint32), ("interior", C.c_int32), ("primary_edges", C.c_int32),
                 ("secondary_edges", C.c_int32), ("use_bvh", C.c_int32), ("exclude_flagged", C.c_int32),
                 ("num_threads", C.c_int32), ("unit_mask", C.c_void_p),
-                ("dir_mode", C.c_int32), ("dir_log", C.c_void_p)]
+                ("dir_mode", C.c_int32), ("dir_log", C.c_void_p),
+                ("edge_pdf", C.c_void_p), ("mix", C.c_double), ("mix_terms", C.c_int32)]
 
 
 class _Outputs(C.Structure):
     _fields_ = [("image", C.c_void_p), ("d_image", C.c_void_p), ("d_vertices", C.c_void_p),
                 ("d_albedo", C.c_void_p), ("d_camera", C.c_void_p), ("mass_vertices", C.c_void_p),
                 ("mass_albedo", C.c_void_p), ("mass_camera", C.c_void_p), ("unit_flags", C.c_void_p),
-                ("stats", C.c_void_p)]
+                ("stats", C.c_void_p), ("edge_stats", C.c_void_p)]
 
 
 _lib = None
@@ -117,9 +118,12 @@ def _camera_struct(cam, keep=None, params64=None):
 def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, primary=True,
            secondary=True, use_bvh=True, exclude_flagged=False, threads=1, unit_mask=None,
            view_id=0, want_flags=False, vertices64=None, albedo64=None, camera64=None,
-           dir_mode=0, dir_log=None):
+           dir_mode=0, dir_log=None, edge_pdf=None, mix=0.0, mix_terms=3, edge_stats=False):
     """Returns a dict with image, (if d_image) d_vertices, d_albedo, d_camera,
-    the matching mass arrays, unit flags and stats."""
+    the matching mass arrays, unit flags and stats; with edge_stats=True also
+    the per-edge harvest statistic. edge_pdf (a distribution over all edges)
+    and mix in [0, 1) select the proposal mixture (mix_terms: bit 0 primary,
+    bit 1 secondary)."""
     keep = []
     s = _scene_struct(scene, keep, vertices64, albedo64)
     c = _camera_struct(cam, keep, camera64)
@@ -129,8 +133,10 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
     mask = None if unit_mask is None else np.ascontiguousarray(unit_mask, np.uint8)
     if dir_mode:
         assert dir_log is not None and dir_log.dtype == np.float64 and dir_log.size == M * 64
+    q = None if edge_pdf is None else np.ascontiguousarray(edge_pdf, np.float64)
     o = _Options(spp, max_depth, seed, view_id, int(interior), int(primary), int(secondary),
-                 int(use_bvh), int(exclude_flagged), threads, _ptr(mask), int(dir_mode), _ptr(dir_log))
+                 int(use_bvh), int(exclude_flagged), threads, _ptr(mask), int(dir_mode), _ptr(dir_log),
+                 _ptr(q), float(mix), int(mix_terms))
     res = {"image": np.zeros((Hw, Ww), np.float64), "stats": np.zeros(8, np.int64)}
     if d_image is not None:
         dimg = np.ascontiguousarray(np.broadcast_to(np.asarray(d_image, np.float64), (Hw, Ww)))
@@ -143,9 +149,12 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
         dimg = None
     if want_flags:
         res["unit_flags"] = np.zeros(M, np.uint8)
+    if edge_stats and d_image is not None:
+        res["edge_stats"] = np.zeros(num_edges(scene), np.float64)
     out = _Outputs(_ptr(res["image"]), _ptr(dimg), _ptr(res.get("d_vertices")), _ptr(res.get("d_albedo")),
                    _ptr(res.get("d_camera")), _ptr(res.get("mass_vertices")), _ptr(res.get("mass_albedo")),
-                   _ptr(res.get("mass_camera")), _ptr(res.get("unit_flags")), _ptr(res["stats"]))
+                   _ptr(res.get("mass_camera")), _ptr(res.get("unit_flags")), _ptr(res["stats"]),
+                   _ptr(res.get("edge_stats")))
     rc = lib().orc_render(C.byref(s), C.byref(c), C.byref(o), C.byref(out))
     if rc != 0:
         raise RuntimeError(f"orc_render failed with code {rc}")
@@ -154,7 +163,7 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
 
 TIE_REASONS = ["near_miss_in_front", "equal_t_hits", "hit_near_edge", "hit_near_tmin", "grazing_hit",
                "shadow_near_edge", "shadow_near_ends", "cdf_tie", "inside_box_tie", "horizon_tie",
-               "vsphere_tie", "branch_tie", "ill_conditioned_edge", "pixel_boundary", "silhouette_sign"]
+               "vsphere_tie", "branch_tie", "ill_conditioned_edge", "pixel_boundary", "silhouette_sign", "mixture_component"]
 
 
 def tie_reasons(reset=True):
@@ -169,6 +178,16 @@ def philox4x32_10(ctr, key):
     o = (C.c_uint32 * 4)()
     lib().orc_philox4x32_10(c, k, o)
     return [int(x) for x in o]
+
+
+def num_edges(scene):
+    keep = []
+    s = _scene_struct(scene, keep)
+    n = C.c_int32()
+    rc = lib().orc_edges(C.byref(s), C.byref(n), None)
+    if rc:
+        raise RuntimeError(f"orc_edges failed {rc}")
+    return int(n.value)
 
 
 def edges(scene):
@@ -211,6 +230,21 @@ def edge_tree_pdf(scene, cam, p, n):
     if rc:
         raise RuntimeError(f"orc_edge_tree_pdf failed {rc}")
     return pdf, fail.value
+
+
+def edge_tree_pdf_of(scene, cam, p, n, edge_ids):
+    """Descent probability of each given edge, by its root-to-leaf path."""
+    keep = []
+    s = _scene_struct(scene, keep)
+    c = _camera_struct(cam)
+    ids = np.ascontiguousarray(edge_ids, np.int32)
+    pdf = np.zeros(ids.size, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    n = np.ascontiguousarray(n, np.float64)
+    rc = lib().orc_edge_tree_pdf_of(C.byref(s), C.byref(c), _vp(p), _vp(n), ids.size, _vp(ids), _vp(pdf))
+    if rc:
+        raise RuntimeError(f"orc_edge_tree_pdf_of failed {rc}")
+    return pdf
 
 
 def edge_tree_sample(scene, cam, p, n, u):

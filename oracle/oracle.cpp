@@ -516,6 +516,8 @@ struct View {
     std::vector<double> pcdf;
     double psum = 0;
     bool tie = false;
+    // proposal mixture of the primary edge choice: P(e) = (1 - mix) len_e / psum + mix q_e
+    std::vector<double> mprob, mcdf;
 };
 
 // Window clip of the screen segment A + l (B - A), l in [t0, t1].
@@ -612,6 +614,22 @@ void build_view(const Scn& s, const orc_camera& oc, View& vw) {
     if (acc > 0) for (double& x : vw.pcdf) x /= acc;
 }
 
+// Mixture of the screen-length edge pdf with a given distribution q over all
+// edges (the learned proposal): weights, running sum, normalised CDF.
+void build_view_mix(const View& vwc, const double* q, double mix, View& vw) {
+    size_t E = vwc.pe.size();
+    vw.mprob.assign(E, 0.0);
+    vw.mcdf.assign(E, 0.0);
+    if (!(vwc.psum > 0)) return;
+    double acc = 0;
+    for (size_t i = 0; i < E; ++i) {
+        vw.mprob[i] = (1.0 - mix) * (vwc.pe[i].len / vwc.psum) + mix * q[i];
+        acc += vw.mprob[i];
+        vw.mcdf[i] = acc;
+    }
+    for (size_t i = 0; i < E; ++i) { vw.mprob[i] /= acc; vw.mcdf[i] /= acc; }
+}
+
 // Index of the first CDF entry greater than u; flags near ties.
 int cdf_pick(const std::vector<double>& cdf, double u, Unit& U) {
     int i = (int)(std::upper_bound(cdf.begin(), cdf.end(), u) - cdf.begin());
@@ -639,6 +657,9 @@ struct ETree {
     int root[2] = {-1, -1};
     V3d cam;
     int max_depth = 0;
+    std::vector<int> parent;    // per node (-1 at the two roots)
+    std::vector<int> leaf_of;   // per edge: its leaf node, -1 if in neither hierarchy
+    std::vector<int> which;     // per node: 0 = H1, 1 = H2
 };
 
 uint32_t spread10(uint32_t x) {
@@ -752,6 +773,22 @@ int build_etree(const Scn& s, const V3d& cam, ETree& t) {
             }
         }
         t.root[h] = build_tree_rec(t, keys, sid, 0, (int)ord.size() - 1, leaves, 0);
+    }
+    t.parent.assign(t.nodes.size(), -1);
+    t.which.assign(t.nodes.size(), 0);
+    t.leaf_of.assign(s.edges.size(), -1);
+    for (int h = 0; h < 2; ++h) {
+        if (t.root[h] < 0) continue;
+        std::vector<int> todo{t.root[h]};
+        while (!todo.empty()) {
+            int n = todo.back();
+            todo.pop_back();
+            t.which[n] = h;
+            const ENode& nd = t.nodes[n];
+            if (nd.edge >= 0) { t.leaf_of[nd.edge] = n; continue; }
+            t.parent[nd.left] = n; t.parent[nd.right] = n;
+            todo.push_back(nd.left); todo.push_back(nd.right);
+        }
     }
     return t.max_depth + 1 > kMaxLevels ? ORC_EDEPTH : ORC_OK;
 }
@@ -893,6 +930,34 @@ void tree_enumerate(const TreeQuery& q, int node, bool h2, double prob, std::vec
     if (wl + wr <= 0) { fail += prob; return; }
     if (wl > 0) tree_enumerate(q, n.left, h2, prob * (wl / (wl + wr)), pdf, fail);
     if (wr > 0) tree_enumerate(q, n.right, h2, prob * (wr / (wl + wr)), pdf, fail);
+}
+
+// Probability that the descent of tree_sample ends at edge e: the product of
+// the branch probabilities along the unique root-to-leaf path of e (root choice
+// included), with the same near-tie flags as a descent along that path.
+double tree_pdf_edge(const TreeQuery& q, int e, Unit* U) {
+    const ETree& t = *q.t;
+    int leaf = t.leaf_of[e];
+    if (leaf < 0) return 0.0;
+    std::vector<int> path;
+    for (int n = leaf; n >= 0; n = t.parent[n]) path.push_back(n);
+    std::reverse(path.begin(), path.end());
+    int h = t.which[leaf];
+    double lo[3], hi[3];
+    root_box(t, lo, hi);
+    double w[2] = {0, 0};
+    for (int r = 0; r < 2; ++r)
+        if (t.root[r] >= 0) w[r] = importance(q, t.nodes[t.root[r]], r == 1, lo, hi, U);
+    if (w[0] + w[1] <= 0) return 0.0;
+    double pdf = w[h] / (w[0] + w[1]);
+    for (size_t i = 0; i + 1 < path.size(); ++i) {
+        const ENode& n = t.nodes[path[i]];
+        double wl = importance(q, t.nodes[n.left], h == 1, n.lo, n.hi, U);
+        double wr = importance(q, t.nodes[n.right], h == 1, n.lo, n.hi, U);
+        if (wl + wr <= 0) return 0.0;
+        pdf *= (path[i + 1] == n.left ? wl : wr) / (wl + wr);
+    }
+    return pdf;
 }
 
 // ---------------------------------------------------------------------------
@@ -1111,10 +1176,12 @@ struct Ctx {
     const double* d_image;
     int Ww, Hw, spp, M, V, T;
     uint32_t k0, k1;
+    std::vector<double> qcdf;   // CDF of the proposal distribution over all edges (secondary mixture)
+    bool mix_p = false, mix_s = false, harvest = false;
 };
 
 struct Acc {
-    std::vector<double> img, g, mass;
+    std::vector<double> img, g, mass, es;
     int64_t rays = 0, flagged = 0, pedge = 0, sedge = 0;
 };
 
@@ -1184,6 +1251,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
     // Rounding scale of each part: a boundary sample's weight is a difference
     // of two radiances, whose rounding error scales with |a| + |b|.
     std::vector<double> scales;
+    std::vector<std::pair<int, double>> harvest;   // (edge, P |c|^2)
     int64_t used_p = 0, used_s = 0;
     if (C.d_image) {
         double wimg = C.d_image[pix] / C.spp;
@@ -1205,11 +1273,29 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 double pdf = 0;
                 double cache[4];
                 int cached = -1;
-                int ei = tree_sample(q, b0[0], [&](int lev) {
+                auto level_u = [&](int lev) {
                     int blk = 1 + lev / 4;
                     if (blk != cached) { rk.block((uint32_t)blk, cache); cached = blk; }
                     return cache[lev % 4];
-                }, pdf, &U, dbg);
+                };
+                int ei;
+                if (C.mix_s) {
+                    // proposal mixture: the component from the block's third
+                    // uniform, a proposal draw from its fourth
+                    if (std::fabs(b0[2] - o.mix) < kTieU) TIE(U, 15);
+                    double pt;
+                    if (b0[2] < o.mix) {
+                        ei = cdf_pick(C.qcdf, b0[3], U);
+                        pt = tree_pdf_edge(q, ei, &U);
+                    } else {
+                        ei = tree_sample(q, b0[0], level_u, pt, &U, dbg);
+                        if (ei < 0) continue;
+                    }
+                    pdf = o.mix * o.edge_pdf[ei] + (1.0 - o.mix) * pt;
+                    if (!(pdf > 0)) continue;
+                } else {
+                    ei = tree_sample(q, b0[0], level_u, pdf, &U, dbg);
+                }
                 if (ei < 0) continue;
                 const Edge& e = s.edges[ei];
                 if (e.f0 == pv.tri || e.f1 == pv.tri) continue;
@@ -1248,6 +1334,10 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                     std::fprintf(stderr, "unit %d vertex %d tri %d p=(%.9g %.9g %.9g) n=(%.9g %.9g %.9g) edge %d pdf %.9g "
                                  "t %.9g Lp %.9g Lm %.9g cos %.9g W %.9g wgt %.9g kappa %.3g\n",
                                  m, k, pv.tri, p.x, p.y, p.z, nsv.x, nsv.y, nsv.z, ei, pdf, b0[1], Lp, Lm, cosw, W, wgt, kap_s);
+                if (C.harvest) {
+                    double c2 = (dot(cross(v1p, wh), cross(v1p, wh)) + dot(cross(wh, v0p), cross(wh, v0p))) * wgt * wgt;
+                    harvest.push_back({ei, pdf * c2});
+                }
                 V3<D> A = Ed.P(e.va), B = Ed.P(e.vb);
                 D beta = dot(lift<D>(wh), cross(A - pv.x, B - pv.x));
                 parts.emplace_back();
@@ -1263,8 +1353,12 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             rp.block(0, b0);
             // stratified edge choice: unit m draws its uniform in [m/M, (m+1)/M)
             double us = ((double)m + b0[0]) / (double)C.M;
-            int ei = cdf_pick(vw.pcdf, us, U);
+            int ei = cdf_pick(C.mix_p ? vw.mcdf : vw.pcdf, us, U);
             const PEdge& pe = vw.pe[ei];
+            // 1 / (P(edge) p(point | edge)), p uniform on the clipped segment
+            double inv_p = C.mix_p ? pe.len / vw.mprob[ei] : vw.psum;
+            double p_edge = C.mix_p ? vw.mprob[ei] : pe.len / vw.psum;
+            if (pe.len > 0) {
             double t = b0[1];
             double x = pe.Ac[0] + (pe.Bc[0] - pe.Ac[0]) * t, y = pe.Ac[1] + (pe.Bc[1] - pe.Ac[1]) * t;
             double nl = std::hypot(pe.Aa[0] - pe.Ba[0], pe.Aa[1] - pe.Ba[1]);
@@ -1299,7 +1393,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             used_p++;
             if (fu != fl) {
                 int ppix = (iy - vw.y0) * C.Ww + (ix - vw.x0);
-                double wgt = C.d_image[ppix] * (fu - fl) * vw.psum / ((double)C.M * nl);
+                double wgt = C.d_image[ppix] * (fu - fl) * inv_p / ((double)C.M * nl);
                 const Edge& e = s.edges[ei];
                 V3<D> a3, b3;
                 alpha_points(cam, Ed.P(e.va), Ed.P(e.vb), a3, b3);
@@ -1310,6 +1404,14 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 parts.emplace_back();
                 scales.push_back((1.0 + kCondSafety * kap_p / kOpsU32) * (std::fabs(fu) + std::fabs(fl)) / std::fabs(fu - fl));
                 sweep(C, L, alpha.i, wgt, parts.back());
+                if (C.harvest) {
+                    double c2 = 0;
+                    for (const auto& pr : parts.back())
+                        if (pr.first / 3 == e.va || pr.first / 3 == e.vb)
+                            if (pr.first < 3 * C.V) c2 += pr.second * pr.second;
+                    harvest.push_back({ei, p_edge * c2});
+                }
+            }
             }
         }
     }
@@ -1326,6 +1428,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             acc.g[pr.first] += pr.second;
             acc.mass[pr.first] += std::fabs(pr.second) * scales[i];
         }
+    for (const auto& h : harvest) acc.es[h.first] += h.second;
 }
 
 }  // namespace
@@ -1401,6 +1504,17 @@ int orc_edge_tree_pdf(const orc_scene* sd, const orc_camera* c, const double p[3
     return ORC_OK;
 }
 
+int orc_edge_tree_pdf_of(const orc_scene* sd, const orc_camera* c, const double p[3], const double n[3],
+                         int32_t count, const int32_t* edges, double* pdf) {
+    Scn s;
+    ETree t;
+    int rc = tree_setup(sd, c, s, t);
+    if (rc) return rc;
+    TreeQuery q{&s, &t, V3d{p[0], p[1], p[2]}, V3d{n[0], n[1], n[2]}, -1};
+    for (int i = 0; i < count; ++i) pdf[i] = tree_pdf_edge(q, edges[i], nullptr);
+    return ORC_OK;
+}
+
 int orc_edge_tree_sample(const orc_scene* sd, const orc_camera* c, const double p[3], const double n[3], int32_t count,
                          const double* u, int32_t* edge, double* pdf) {
     Scn s;
@@ -1468,6 +1582,18 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
     }
     Ctx C;
     C.s = &s; C.oc = oc; C.o = o; C.vw = &vw; C.et = need_tree ? &et : nullptr;
+    bool mix = o->edge_pdf && o->mix > 0;
+    if (mix && !(o->mix < 1)) return ORC_EINVAL;
+    C.mix_p = mix && (o->mix_terms & 1);
+    C.mix_s = mix && (o->mix_terms & 2) && need_tree;
+    if (C.mix_p) build_view_mix(vw, o->edge_pdf, o->mix, vw);
+    if (C.mix_s) {
+        C.qcdf.assign(s.edges.size(), 0.0);
+        double acc = 0;
+        for (size_t i = 0; i < s.edges.size(); ++i) { acc += o->edge_pdf[i]; C.qcdf[i] = acc; }
+        for (double& x : C.qcdf) x /= acc;
+    }
+    C.harvest = out->edge_stats != nullptr && out->d_image != nullptr;
     C.d_image = out->d_image;
     C.Ww = oc->win_x1 - oc->win_x0; C.Hw = oc->win_y1 - oc->win_y0;
     C.spp = o->spp;
@@ -1481,6 +1607,7 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
         if (out->image) a.img.assign((size_t)C.Ww * C.Hw, 0.0);
         a.g.assign(np, 0.0);
         a.mass.assign(np, 0.0);
+        if (C.harvest) a.es.assign(s.edges.size(), 0.0);
     }
 #ifdef _OPENMP
 #pragma omp parallel for num_threads(nth) schedule(dynamic, 64)
@@ -1507,6 +1634,11 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
         for (size_t i = 0; i < tot.img.size(); ++i) tot.img[i] += a.img[i];
         for (int i = 0; i < np; ++i) { tot.g[i] += a.g[i]; tot.mass[i] += a.mass[i]; }
         tot.rays += a.rays; tot.flagged += a.flagged; tot.pedge += a.pedge; tot.sedge += a.sedge;
+    }
+    if (C.harvest) {
+        for (size_t i = 0; i < s.edges.size(); ++i) out->edge_stats[i] = 0;
+        for (Acc& a : accs)
+            for (size_t i = 0; i < s.edges.size(); ++i) out->edge_stats[i] += a.es[i];
     }
     if (out->image) for (size_t i = 0; i < tot.img.size(); ++i) out->image[i] = tot.img[i];
     if (out->d_image) {

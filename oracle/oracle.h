@@ -63,6 +63,14 @@ typedef struct {
      * factors into dir_log, 2 = replay them instead of sampling. [M][64]. */
     int32_t dir_mode;
     double* dir_log;
+    /* Proposal mixture: edge_pdf[E] is a distribution over all edges (edge ids
+     * as orc_edges numbers them); an edge is drawn from it with probability
+     * mix and from the plain sampler otherwise, and every sample is weighted
+     * by the mixture pdf. mix_terms: bit 0 = primary edges, bit 1 = secondary
+     * edges. mix = 0 or edge_pdf = NULL: plain sampling. */
+    const double* edge_pdf;
+    double  mix;
+    int32_t mix_terms;
 } orc_options;
 
 typedef struct {
@@ -77,6 +85,9 @@ typedef struct {
     double* mass_camera;         /* [9] or NULL */
     uint8_t* unit_flags;         /* [M] or NULL: 1 = a decision was within rounding of a tie */
     int64_t* stats;              /* [8] or NULL: rays, flagged units, edge samples used, ... */
+    double* edge_stats;          /* [E] or NULL: per edge, sum over its boundary samples (primary and
+                                    secondary) of P * |c|^2, P the probability with which the edge was
+                                    drawn, c the sample's contribution to the edge's two endpoints */
 } orc_outputs;
 
 /* Error codes (0 = ok). */
@@ -102,6 +113,10 @@ int  orc_closest_hit(const orc_scene* s, int32_t n, const double* o, const doubl
 int  orc_edge_tree_pdf(const orc_scene* s, const orc_camera* c, const double p[3],
                        const double n[3], double* pdf, double* p_fail);
 
+/* Probability that one descent ends at each of the given edges (the product of
+ * branch probabilities along each edge's root-to-leaf path). */
+int  orc_edge_tree_pdf_of(const orc_scene* s, const orc_camera* c, const double p[3],
+                          const double n[3], int32_t count, const int32_t* edges, double* pdf);
 /* One descent per row of u (u[i][0] = root uniform, u[i][1..64] = level uniforms). */
 int  orc_edge_tree_sample(const orc_scene* s, const orc_camera* c, const double p[3],
                           const double n[3], int32_t count, const double* u,

@@ -416,3 +416,33 @@ def config3(seed=0):
 
 
 CONFIGS = {"config1": config1, "config2": config2, "config3": config3}
+
+
+# ---------------------------------------------------------------------------
+# learned edge proposal: seeded network parameters and synthetic inputs
+# ---------------------------------------------------------------------------
+MLP_PARAMS = 32 * 64 + 64 + 64 * 64 + 64 + 64 + 1    # W1 | b1 | W2 | b2 | W3 | b3
+
+
+def mlp_params(seed: int, bias_scale: float = 0.0) -> np.ndarray:
+    """He-style random initial parameters (float32, W1 [32][64] | b1 [64] |
+    W2 [64][64] | b2 [64] | W3 [64] | b3 [1]); biases N(0, bias_scale)."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    th = np.zeros(MLP_PARAMS, np.float32)
+    o = 0
+    for rows, cols, fan in ((32, 64, 29), (64, 64, 64), (64, 1, 64)):
+        th[o:o + rows * cols] = rng.normal(0.0, np.sqrt(2.0 / fan), rows * cols)
+        o += rows * cols
+        th[o:o + cols] = rng.normal(0.0, bias_scale, cols) if bias_scale > 0 else 0.0
+        o += cols
+    assert o == MLP_PARAMS
+    return th
+
+
+def mlp_inputs(seed: int, n: int) -> np.ndarray:
+    """Synthetic [n][32] float32 inputs with the value ranges of edge features
+    (29 used columns, zero padding)."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    x = np.zeros((n, 32), np.float32)
+    x[:, :29] = rng.normal(0.0, 1.0, (n, 29))
+    return x
