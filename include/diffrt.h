@@ -93,6 +93,24 @@ typedef struct {
     uint32_t terms;              /* DR_TERM_* bits; 0 means DR_TERM_ALL */
     const uint8_t* unit_mask;    /* [M] device, or NULL. M = window pixels * spp; unit m
                                     = pixel sample m plus primary edge sample m; 0 = skip */
+    /* Learned edge proposal (used by drRenderBackward only). edge_pdf[E]
+     * (device) is a distribution over all edges, indexed by edge id: edges are
+     * the unique undirected edges of the triangles, numbered in increasing
+     * order of (smaller vertex index, larger vertex index). With edge_mix in
+     * (0, 1) each edge sample of the terms in edge_mix_terms is drawn from
+     * edge_pdf with probability edge_mix and from the plain sampler otherwise,
+     * and weighted by the mixture pdf (importance sampling stays unbiased: the
+     * mixture is positive wherever the plain pdf is). edge_mix = 0 or
+     * edge_pdf = NULL: plain sampling. */
+    const float* edge_pdf;
+    float    edge_mix;
+    uint32_t edge_mix_terms;     /* DR_TERM_PRIMARY | DR_TERM_SECONDARY; 0 means both */
+    /* If not NULL, [E] device, overwritten: per edge, the sum over its boundary
+     * samples (primary and secondary) of P * |c|^2, where P is the probability
+     * with which the sample drew the edge and c its contribution to the edge's
+     * two endpoints (6 numbers). Its expectation does not depend on the
+     * sampler: the training target of the learned proposal. */
+    float*   edge_stats;
 } drRenderOptions;
 
 /* Creates a scene: validates sizes and indices (host copy of the topology),
@@ -123,6 +141,48 @@ drStatus drRenderBackward(drScene scene, const drCamera* camera, const drRenderO
  * loops (the thesis optimises with Adam, Ch. 5 Results). */
 drStatus drAdamStep(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1,
                     float beta2, float eps, int64_t step, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned edge proposal. The thesis samples edges by importance with a
+ * hand-built pdf (Ch. 5, Importance Sampling the Edges) and names what such a
+ * pdf should follow; these entry points train and evaluate a small network
+ * that proposes a per-view distribution over edges from per-(edge, view)
+ * features, for the mixture in drRenderOptions.
+ *
+ * Network: 32 inputs -> 64 (ReLU) -> 64 (ReLU) -> 1 logit. Parameters theta
+ * are DR_MLP_PARAMS FP32 numbers (device), row-major:
+ *   W1 [32][64] | b1 [64] | W2 [64][64] | b2 [64] | W3 [64] | b3 [1].
+ * Inputs and weight matrices are rounded to BF16 for the matrix cores;
+ * activations, gradients, biases and logits are FP32 (FP32 accumulation).
+ * All arrays are device memory owned by the caller; errors: NULL pointers or
+ * negative sizes give DR_ERROR_INVALID_VALUE; launch failures DR_ERROR_DEVICE.
+ * ------------------------------------------------------------------------- */
+#define DR_MLP_PARAMS 6337
+#define DR_EDGE_FEATURES 32
+
+/* features[E][32] of every edge seen from `camera`: endpoints and face
+ * normals in the camera frame, endpoints in world space, albedo and emission
+ * of both faces, boundary flag, cosine between the face normals, normalised
+ * screen coordinates of the endpoints (depth clamped to the near plane,
+ * clamped to +-8), edge length, zero padding. */
+drStatus drEdgeFeatures(drScene scene, const drCamera* camera, float* features, hipStream_t stream);
+
+/* logits[n] of the rows x[n][32]. */
+drStatus drMlpForward(const float* theta, const float* x, int32_t n, float* logits, hipStream_t stream);
+
+/* Per view v (rows offsets[v] .. offsets[v+1]-1; offsets[n_views+1] int32,
+ * device): prob = softmax(logits) (if prob != NULL); if target != NULL, with
+ * t = target / sum(target) over the view: view_loss[v] = -sum t log prob
+ * (0 for views whose target sums to 0) and d_logits = (prob - t) / (number of
+ * views whose target sum is positive), the gradient of the mean loss.
+ * scratch: n_views floats. */
+drStatus drMlpSoftmaxXent(const float* logits, const float* target, const int32_t* offsets, int32_t n_views,
+                          float* prob, float* d_logits, float* view_loss, float* scratch, hipStream_t stream);
+
+/* grad[DR_MLP_PARAMS] (overwritten) = gradient of sum_i d_logits[i] * logits[i]
+ * w.r.t. theta (BF16 rounding passes gradients through unchanged). */
+drStatus drMlpBackward(const float* theta, const float* x, int32_t n, const float* d_logits, float* grad,
+                       hipStream_t stream);
 
 /* Measurement support (not needed for rendering). With `events` on, every
  * forward, primary-edge and path-backward kernel launch is bracketed by HIP

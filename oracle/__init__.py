@@ -55,7 +55,7 @@ class _Outputs(C.Structure):
     _fields_ = [("image", C.c_void_p), ("d_image", C.c_void_p), ("d_vertices", C.c_void_p),
                 ("d_albedo", C.c_void_p), ("d_camera", C.c_void_p), ("mass_vertices", C.c_void_p),
                 ("mass_albedo", C.c_void_p), ("mass_camera", C.c_void_p), ("unit_flags", C.c_void_p),
-                ("stats", C.c_void_p), ("edge_stats", C.c_void_p)]
+                ("stats", C.c_void_p), ("edge_stats", C.c_void_p), ("edge_stats_mass", C.c_void_p)]
 
 
 _lib = None
@@ -151,10 +151,11 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
         res["unit_flags"] = np.zeros(M, np.uint8)
     if edge_stats and d_image is not None:
         res["edge_stats"] = np.zeros(num_edges(scene), np.float64)
+        res["edge_stats_mass"] = np.zeros(num_edges(scene), np.float64)
     out = _Outputs(_ptr(res["image"]), _ptr(dimg), _ptr(res.get("d_vertices")), _ptr(res.get("d_albedo")),
                    _ptr(res.get("d_camera")), _ptr(res.get("mass_vertices")), _ptr(res.get("mass_albedo")),
                    _ptr(res.get("mass_camera")), _ptr(res.get("unit_flags")), _ptr(res["stats"]),
-                   _ptr(res.get("edge_stats")))
+                   _ptr(res.get("edge_stats")), _ptr(res.get("edge_stats_mass")))
     rc = lib().orc_render(C.byref(s), C.byref(c), C.byref(o), C.byref(out))
     if rc != 0:
         raise RuntimeError(f"orc_render failed with code {rc}")

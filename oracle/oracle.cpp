@@ -1181,7 +1181,7 @@ struct Ctx {
 };
 
 struct Acc {
-    std::vector<double> img, g, mass, es;
+    std::vector<double> img, g, mass, es, esm;
     int64_t rays = 0, flagged = 0, pedge = 0, sedge = 0;
 };
 
@@ -1251,7 +1251,8 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
     // Rounding scale of each part: a boundary sample's weight is a difference
     // of two radiances, whose rounding error scales with |a| + |b|.
     std::vector<double> scales;
-    std::vector<std::pair<int, double>> harvest;   // (edge, P |c|^2)
+    struct Harvest { int e; double v, mass; };
+    std::vector<Harvest> harvest;   // (edge, P |c|^2, its rounding scale)
     int64_t used_p = 0, used_s = 0;
     if (C.d_image) {
         double wimg = C.d_image[pix] / C.spp;
@@ -1334,15 +1335,15 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                     std::fprintf(stderr, "unit %d vertex %d tri %d p=(%.9g %.9g %.9g) n=(%.9g %.9g %.9g) edge %d pdf %.9g "
                                  "t %.9g Lp %.9g Lm %.9g cos %.9g W %.9g wgt %.9g kappa %.3g\n",
                                  m, k, pv.tri, p.x, p.y, p.z, nsv.x, nsv.y, nsv.z, ei, pdf, b0[1], Lp, Lm, cosw, W, wgt, kap_s);
-                if (C.harvest) {
-                    double c2 = (dot(cross(v1p, wh), cross(v1p, wh)) + dot(cross(wh, v0p), cross(wh, v0p))) * wgt * wgt;
-                    harvest.push_back({ei, pdf * c2});
-                }
                 V3<D> A = Ed.P(e.va), B = Ed.P(e.vb);
                 D beta = dot(lift<D>(wh), cross(A - pv.x, B - pv.x));
                 parts.emplace_back();
                 scales.push_back((1.0 + kCondSafety * kap_s / kOpsU32) * (std::fabs(Fp) + std::fabs(Fm)) / std::fabs(Fp - Fm));
                 sweep(C, L, beta.i, wgt, parts.back());
+                if (C.harvest) {
+                    double c2 = (dot(cross(v1p, wh), cross(v1p, wh)) + dot(cross(wh, v0p), cross(wh, v0p))) * wgt * wgt;
+                    harvest.push_back({ei, pdf * c2, pdf * c2 * scales.back()});
+                }
             }
         }
         // Primary boundary term: one screen-space edge sample for this unit.
@@ -1409,7 +1410,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                     for (const auto& pr : parts.back())
                         if (pr.first / 3 == e.va || pr.first / 3 == e.vb)
                             if (pr.first < 3 * C.V) c2 += pr.second * pr.second;
-                    harvest.push_back({ei, p_edge * c2});
+                    harvest.push_back({ei, p_edge * c2, p_edge * c2 * scales.back()});
                 }
             }
             }
@@ -1428,7 +1429,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             acc.g[pr.first] += pr.second;
             acc.mass[pr.first] += std::fabs(pr.second) * scales[i];
         }
-    for (const auto& h : harvest) acc.es[h.first] += h.second;
+    for (const auto& h : harvest) { acc.es[h.e] += h.v; acc.esm[h.e] += h.mass; }
 }
 
 }  // namespace
@@ -1607,7 +1608,7 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
         if (out->image) a.img.assign((size_t)C.Ww * C.Hw, 0.0);
         a.g.assign(np, 0.0);
         a.mass.assign(np, 0.0);
-        if (C.harvest) a.es.assign(s.edges.size(), 0.0);
+        if (C.harvest) { a.es.assign(s.edges.size(), 0.0); a.esm.assign(s.edges.size(), 0.0); }
     }
 #ifdef _OPENMP
 #pragma omp parallel for num_threads(nth) schedule(dynamic, 64)
@@ -1637,8 +1638,12 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
     }
     if (C.harvest) {
         for (size_t i = 0; i < s.edges.size(); ++i) out->edge_stats[i] = 0;
+        if (out->edge_stats_mass) for (size_t i = 0; i < s.edges.size(); ++i) out->edge_stats_mass[i] = 0;
         for (Acc& a : accs)
-            for (size_t i = 0; i < s.edges.size(); ++i) out->edge_stats[i] += a.es[i];
+            for (size_t i = 0; i < s.edges.size(); ++i) {
+                out->edge_stats[i] += a.es[i];
+                if (out->edge_stats_mass) out->edge_stats_mass[i] += a.esm[i];
+            }
     }
     if (out->image) for (size_t i = 0; i < tot.img.size(); ++i) out->image[i] = tot.img[i];
     if (out->d_image) {

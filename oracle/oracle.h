@@ -88,6 +88,8 @@ typedef struct {
     double* edge_stats;          /* [E] or NULL: per edge, sum over its boundary samples (primary and
                                     secondary) of P * |c|^2, P the probability with which the edge was
                                     drawn, c the sample's contribution to the edge's two endpoints */
+    double* edge_stats_mass;     /* [E] or NULL: the same sum with each term scaled by its contribution's
+                                    rounding scale (as in the mass arrays) */
 } orc_outputs;
 
 /* Error codes (0 = ok). */

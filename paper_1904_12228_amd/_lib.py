@@ -20,7 +20,10 @@ DR_TERM_ALL = 7
 # every entry point declared in include/diffrt.h
 EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneGetInfo", "drRender", "drRenderBackward",
            "drAdamStep", "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy",
-           "drGetErrorString"]
+           "drGetErrorString", "drEdgeFeatures", "drMlpForward", "drMlpSoftmaxXent", "drMlpBackward"]
+
+MLP_PARAMS = 6337
+EDGE_FEATURES = 32
 
 
 class SceneDesc(C.Structure):
@@ -38,7 +41,9 @@ class Camera(C.Structure):
 
 class RenderOptions(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
-                ("view_id", C.c_uint32), ("terms", C.c_uint32), ("unit_mask", C.c_void_p)]
+                ("view_id", C.c_uint32), ("terms", C.c_uint32), ("unit_mask", C.c_void_p),
+                ("edge_pdf", C.c_void_p), ("edge_mix", C.c_float), ("edge_mix_terms", C.c_uint32),
+                ("edge_stats", C.c_void_p)]
 
 
 class Profile(C.Structure):

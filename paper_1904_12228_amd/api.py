@@ -39,8 +39,10 @@ def camera_struct(cam) -> _lib.Camera:
     return c
 
 
-def options_struct(spp, max_depth, seed=0, view_id=0, terms=0, unit_mask=None) -> _lib.RenderOptions:
-    return _lib.RenderOptions(int(spp), int(max_depth), int(seed), int(view_id), int(terms), _ptr(unit_mask))
+def options_struct(spp, max_depth, seed=0, view_id=0, terms=0, unit_mask=None, edge_pdf=None, edge_mix=0.0,
+                   edge_mix_terms=0, edge_stats=None) -> _lib.RenderOptions:
+    return _lib.RenderOptions(int(spp), int(max_depth), int(seed), int(view_id), int(terms), _ptr(unit_mask),
+                              _ptr(edge_pdf), float(edge_mix), int(edge_mix_terms), _ptr(edge_stats))
 
 
 class Scene:
@@ -81,7 +83,12 @@ class Scene:
         return img
 
     def render_backward(self, cam, spp, max_depth, d_image, seed=0, view_id=0, terms=0, unit_mask=None,
-                        want=("vertices", "albedo", "camera"), outs=None):
+                        want=("vertices", "albedo", "camera"), outs=None, edge_pdf=None, edge_mix=0.0,
+                        edge_mix_terms=0, edge_stats=None):
+        """Gradients w.r.t. vertices [V,3], albedo [T] and camera [9]. With
+        edge_pdf ([E] device distribution) and edge_mix > 0 the edge samples
+        are drawn from the proposal mixture; edge_stats ([E] float32 device
+        tensor) receives the harvest statistic."""
         d_image = _dev(d_image, torch.float32, self.device)
         if outs is None:
             dv = torch.empty((self.num_vertices, 3), dtype=torch.float32, device=self.device) if "vertices" in want else None
@@ -90,10 +97,23 @@ class Scene:
         else:
             dv, da, dc = outs
         c = camera_struct(cam)
-        o = options_struct(spp, max_depth, seed, view_id, terms, unit_mask)
+        if edge_pdf is not None:
+            assert edge_pdf.dtype == torch.float32 and edge_pdf.is_contiguous() and edge_pdf.numel() == self.num_edges
+        if edge_stats is not None:
+            assert edge_stats.dtype == torch.float32 and edge_stats.is_contiguous() and edge_stats.numel() == self.num_edges
+        o = options_struct(spp, max_depth, seed, view_id, terms, unit_mask, edge_pdf, edge_mix, edge_mix_terms,
+                           edge_stats)
         _lib.check(_lib.load().drRenderBackward(self._h, C.byref(c), C.byref(o), _ptr(d_image), _ptr(dv), _ptr(da),
                                                 _ptr(dc), _stream()), "drRenderBackward")
         return dv, da, dc
+
+    def edge_features(self, cam, out=None):
+        """[E, 32] float32 features of every edge seen from `cam`."""
+        f = out if out is not None else torch.empty((self.num_edges, _lib.EDGE_FEATURES), dtype=torch.float32,
+                                                     device=self.device)
+        c = camera_struct(cam)
+        _lib.check(_lib.load().drEdgeFeatures(self._h, C.byref(c), _ptr(f), _stream()), "drEdgeFeatures")
+        return f
 
     def set_profiling(self, events=True, counters=False):
         _lib.check(_lib.load().drSetProfiling(self._h, int(events), int(counters)), "drSetProfiling")

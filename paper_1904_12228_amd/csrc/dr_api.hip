@@ -68,7 +68,9 @@ static bool valid_camera(const drCamera* c) {
 }
 
 static bool valid_options(const drRenderOptions* o) {
-    return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0;
+    return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0 &&
+           o->edge_mix >= 0.0f && o->edge_mix < 1.0f &&
+           (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) == 0;
 }
 
 static ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {

@@ -560,6 +560,39 @@ __global__ void k_etree_refit(SceneView s, v3 cam, int n, int base, int root_slo
     }
 }
 
+__global__ void k_fill_int(int* __restrict__ x, int n, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+// Parent links of the edge hierarchy: for every child slot of every node,
+// (node << 1 | side) into the child's entry (internal nodes) or the edge's
+// entry (leaves). Child 0 marks an absent root.
+__global__ void k_etree_parents(const ETNode* __restrict__ nodes, int nnodes, int* __restrict__ enpar,
+                                int* __restrict__ eleaf) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nnodes) return;
+    if (n == 0) enpar[0] = -1;
+    for (int side = 0; side < 2; ++side) {
+        int ch = nodes[n].child[side];
+        if (ch > 0) enpar[ch] = (n << 1) | side;
+        else if (ch < 0) eleaf[~ch] = (n << 1) | side;
+    }
+}
+
+__global__ void k_mix_weights(const double* __restrict__ plen, const double* __restrict__ ptot, const float* __restrict__ q,
+                              double mix, int E, double* __restrict__ w) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E) return;
+    double tot = ptot[0];
+    w[i] = (1.0 - mix) * (tot > 0.0 ? plen[i] / tot : 0.0) + mix * (double)q[i];
+}
+
+__global__ void k_to_double(const float* __restrict__ q, int E, double* __restrict__ w) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < E) w[i] = (double)q[i];
+}
+
 __global__ void k_etree_root_init(ETNode* nodes) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ETNode r = {};
@@ -657,9 +690,43 @@ drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool
                                                     s->etree.as<ETNode>(), s->ecode.as<int>(), s->edepth.as<int>());
         base += std::max(m - 1, 0);
     }
+    s->etree_nodes = nnodes;
+    DR_ALLOC(s->eleaf, sizeof(int) * E);
+    DR_ALLOC(s->enpar, sizeof(int) * nnodes);
+    k_fill_int<<<blocks(E, BS), BS, 0, st>>>(s->eleaf.as<int>(), E, -1);
+    k_etree_parents<<<blocks(nnodes, BS), BS, 0, st>>>(s->etree.as<ETNode>(), nnodes, s->enpar.as<int>(),
+                                                       s->eleaf.as<int>());
     s->tree_key = key;
     s->tree_valid = true;
     return DR_SUCCESS;
+}
+
+// Mixture of the primary edge pdf with the proposal q (weights, FP64 scan,
+// normalised CDF with the total at [E]) and the CDF of q alone.
+drStatus build_view_mix(drScene_t* s, const float* q, float mix, bool primary, bool secondary, hipStream_t st) {
+    const int BS = 256;
+    int E = s->E;
+    if (E == 0) return DR_SUCCESS;
+    DR_ALLOC(s->mixw, sizeof(double) * E);
+    size_t tmp = 0;
+    DR_CHECK(hipcub::DeviceScan::InclusiveSum(nullptr, tmp, s->mixw.as<double>(), s->mixw.as<double>(), E, st));
+    DR_ALLOC(s->scan_tmp, tmp + 256);
+    if (primary) {
+        DR_ALLOC(s->mcdf, sizeof(double) * (E + 1));
+        k_mix_weights<<<blocks(E, BS), BS, 0, st>>>(s->plen.as<double>(), s->pcdf.as<double>() + E, q, (double)mix, E,
+                                                    s->mixw.as<double>());
+        DR_CHECK(hipcub::DeviceScan::InclusiveSum(s->scan_tmp.p, tmp, s->mixw.as<double>(), s->mcdf.as<double>(), E, st));
+        k_store_total<<<1, 1, 0, st>>>(s->mcdf.as<double>(), E, s->mcdf.as<double>() + E);
+        k_normalize_cdf<<<blocks(E, BS), BS, 0, st>>>(s->mcdf.as<double>(), E);
+    }
+    if (secondary) {
+        DR_ALLOC(s->qcdf, sizeof(double) * (E + 1));
+        k_to_double<<<blocks(E, BS), BS, 0, st>>>(q, E, s->mixw.as<double>());
+        DR_CHECK(hipcub::DeviceScan::InclusiveSum(s->scan_tmp.p, tmp, s->mixw.as<double>(), s->qcdf.as<double>(), E, st));
+        k_store_total<<<1, 1, 0, st>>>(s->qcdf.as<double>(), E, s->qcdf.as<double>() + E);
+        k_normalize_cdf<<<blocks(E, BS), BS, 0, st>>>(s->qcdf.as<double>(), E);
+    }
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 
 }  // namespace dr

@@ -150,6 +150,8 @@ struct TreeView {
     const ETNode* nodes;     // [0] = virtual root whose children are the H1 and H2 roots
     int valid;               // 0: no edges at all
     v3 cam;
+    const int* eleaf;        // [E] (node << 1 | side) holding the edge's leaf, -1 if in neither tree
+    const int* enpar;        // [nodes] (parent << 1 | side) of each internal node; -1 at the virtual root
 };
 
 enum : int { kErrStack = 1, kErrTreeDepth = 2 };

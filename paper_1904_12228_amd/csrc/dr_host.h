@@ -62,6 +62,10 @@ struct drScene_t {
     dr::Buf pe, plen, pcdf, scan_tmp, ecls, epos, elist, ecode, ecode_s, elist_s, ekeys, eparent, ecounter, etree,
         ebounds, edepth;
     int n1 = 0, n2 = 0;
+    int etree_nodes = 0;
+    // learned-proposal mixture: weights, mixture CDF of primary edges, CDF of
+    // the proposal; edge-tree parent links (node << 1 | side)
+    dr::Buf mixw, mcdf, qcdf, eleaf, enpar;
     dr::ViewKey tree_key{};
     bool tree_valid = false;
     // checkpoints of the last forward pass
@@ -87,6 +91,7 @@ namespace dr {
 // dr_build.hip
 drStatus build_scene_static(drScene_t* s, hipStream_t st);   // kinds, lights, triangles, BVH
 drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool need_tree, hipStream_t st);
+drStatus build_view_mix(drScene_t* s, const float* q, float mix, bool primary, bool secondary, hipStream_t st);
 Cam make_cam(const drCamera& c);
 
 // dr_render.hip

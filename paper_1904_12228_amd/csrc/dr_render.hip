@@ -32,6 +32,17 @@ struct RenderArgs {
     uint8_t* ck_vis;   // [M]
 };
 
+// Learned-proposal mixture and harvest (the <.., MIX = true> kernel variants).
+struct MixArgs {
+    const float* q;          // [E] proposal distribution over edges
+    const double* mcdf;      // [E + 1] mixture CDF of primary edges (total weight at [E])
+    const double* qcdf;      // [E + 1] CDF of q
+    const double* plen;      // [E] clipped screen length of primary edges
+    float mix;               // weight of q
+    int prim, sec;           // mixture on for primary / secondary edges
+    float* estats;           // [E] harvest accumulator, or null
+};
+
 __device__ inline void unit_pixel(const Cam& k, const RenderArgs& a, int m, int& pix, int& px, int& py, uint32_t& sid) {
     pix = m / a.spp;
     int smp = m - pix * a.spp;
@@ -286,10 +297,10 @@ __device__ inline void flush_cam(const CamAcc& ca, float* camacc) {
 // ---------------------------------------------------------------------------
 // primary edge samples (eq. mc): one per unit
 // ---------------------------------------------------------------------------
-template <int STK, bool CNT>
+template <int STK, bool CNT, bool MIX>
 __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
                                                 const double* __restrict__ cdf, const float* __restrict__ d_image,
-                                                float* __restrict__ dV, float* __restrict__ camacc) {
+                                                float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
     __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
@@ -305,7 +316,19 @@ __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a
         float4 b0 = rp.block(0);
         // stratified edge choice: unit m draws its uniform in [m/M, (m+1)/M), so
         // the lanes of a wave take neighbouring edges in CDF order
-        int ei = pick_cdf_d(cdf, s.E, ((double)m + (double)b0.x) / (double)a.M);
+        bool mixp = MIX && mx.prim;
+        int ei = pick_cdf_d(mixp ? mx.mcdf : cdf, s.E, ((double)m + (double)b0.x) / (double)a.M);
+        // 1 / (P(edge) p(point | edge)), the point uniform on the clipped segment
+        double inv_p = total, p_edge = 0.0;
+        bool live = true;
+        if (MIX) {
+            double l = mx.plen[ei];
+            p_edge = mixp ? ((1.0 - (double)mx.mix) * l / total + (double)mx.mix * (double)mx.q[ei]) / mx.mcdf[s.E]
+                          : l / total;
+            live = l > 0.0;
+            if (live) inv_p = l / p_edge;
+        }
+        if (live) {
         PEdge p = pe[ei];
         float t = b0.y;
         float x = p.Ac[0] + (p.Bc[0] - p.Ac[0]) * t, y = p.Ac[1] + (p.Bc[1] - p.Ac[1]) * t;
@@ -328,7 +351,7 @@ __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a
         if (fu != fl) {
             int ix = min(max((int)floorf(x), k.x0), k.x1 - 1);
             int iy = min(max((int)floorf(y), k.y0), k.y1 - 1);
-            float w = d_image[(iy - k.y0) * a.Ww + (ix - k.x0)] * (fu - fl) * (float)(total / (double)a.M) / nl;
+            float w = d_image[(iy - k.y0) * a.Ww + (ix - k.x0)] * (fu - fl) * (float)(inv_p / (double)a.M) / nl;
             // d alpha / d(a, b) (eq. redner_dirac_jacobian) at the sample point
             float gax = w * (By - y), gay = w * (x - Bx);
             float gbx = w * (y - Ay), gby = w * (Ax - x);
@@ -344,6 +367,13 @@ __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a
             gv[0] = ga.x; gv[1] = ga.y; gv[2] = ga.z;
             gv[3] = gb.x; gv[4] = gb.y; gv[5] = gb.z;
             wk.atomics(6);
+            if (MIX && mx.estats) {
+                float c2 = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 6; ++i) c2 += gv[i] * gv[i];
+                atomicAdd(&mx.estats[ei], (float)p_edge * c2);
+            }
+        }
         }
     }
     scatter_grouped(have, key, gv, 4, [&](int ek, int i) {
@@ -466,12 +496,50 @@ __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rn
     }
 }
 
+// Probability that one descent ends at edge e: the product of the branch
+// probabilities along its leaf-to-root path (root choice included).
+template <class W>
+__device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int e, W& wk) {
+    int code = tv.eleaf[e];
+    if (code < 0) return 0.0f;
+    const ETNode* nodes = tv.nodes;
+    int node = code >> 1, side = code & 1;
+    float pdf = 1.0f;
+    for (int guard = 0; guard <= kMaxLevels + 1; ++guard) {
+        const ETNode& N = nodes[node];
+        wk.tree();
+        int pcode = node == 0 ? -1 : tv.enpar[node];
+        float plo[3], phi[3];
+        if (node == 0) {
+            for (int k = 0; k < 3; ++k) { plo[k] = 3e38f; phi[k] = -3e38f; }
+            for (int c = 0; c < 2; ++c)
+                if (N.child[c] != 0)
+                    for (int k = 0; k < 3; ++k) { plo[k] = fminf(plo[k], N.ch[c].lo[k]); phi[k] = fmaxf(phi[k], N.ch[c].hi[k]); }
+        } else {
+            const ETChild& pc = nodes[pcode >> 1].ch[pcode & 1];
+            for (int k = 0; k < 3; ++k) { plo[k] = pc.lo[k]; phi[k] = pc.hi[k]; }
+        }
+        int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
+        float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
+        float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
+        float tot = w0 + w1;
+        if (!(tot > 0.0f)) return 0.0f;
+        pdf *= (side == 0 ? w0 : w1) / tot;
+        if (node == 0) return pdf;
+        node = pcode >> 1;
+        side = pcode & 1;
+    }
+    atomicOr(q.s->err, kErrTreeDepth);
+    return 0.0f;
+}
+
 // ---------------------------------------------------------------------------
 // backward over paths: secondary edges at every vertex + interior adjoint
 // ---------------------------------------------------------------------------
-template <int MAXD, int STK, bool CNT>
+template <int MAXD, int STK, bool CNT, bool MIX>
 __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs a, TreeView tv, const float* __restrict__ d_image,
-                                                 float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc) {
+                                                 float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc,
+                                                 MixArgs mx) {
     __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
@@ -555,7 +623,23 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                 TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
                 float pdf;
                 bool dbg = m == a.debug_unit;
-                int ei = tree_sample(tv, q, rk, b0.x, pdf, wk, dbg);
+                int ei;
+                if (MIX && mx.sec) {
+                    // proposal mixture: component from the third uniform of the
+                    // block, proposal draw from the fourth
+                    float pt;
+                    if (b0.z < mx.mix) {
+                        ei = pick_cdf_d(mx.qcdf, s.E, (double)b0.w);
+                        pt = tree_pdf_edge(tv, q, ei, wk);
+                    } else {
+                        ei = tree_sample(tv, q, rk, b0.x, pt, wk, dbg);
+                        if (ei < 0) continue;
+                    }
+                    pdf = mx.mix * mx.q[ei] + (1.0f - mx.mix) * pt;
+                    if (!(pdf > 0.0f) || s.ekind[ei] == 0) continue;
+                } else {
+                    ei = tree_sample(tv, q, rk, b0.x, pdf, wk, dbg);
+                }
                 if (ei < 0) continue;
                 int4 e = s.edges[ei];
                 if (e.z == tri[kk] || e.w == tri[kk]) continue;
@@ -588,6 +672,10 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                 atomic_add3(dV, e.x, cross(v1p, wh) * wgt);
                 atomic_add3(dV, e.y, cross(wh, v0p) * wgt);
                 wk.atomics(6);
+                if (MIX && mx.estats) {
+                    v3 c0 = cross(v1p, wh), c1 = cross(wh, v0p);
+                    atomicAdd(&mx.estats[ei], pdf * wgt * wgt * (dot(c0, c0) + dot(c1, c1)));
+                }
                 xbar[kk] += (cross(wh, v1p) + cross(v0p, wh)) * wgt;
             }
         }
@@ -778,36 +866,65 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
     k_fill<<<1, 64, 0, st>>>(camacc, 12, 0.0f);
     uint32_t terms = a.terms;
     unsigned long long* cbase = a.counters;
+    // learned-proposal mixture and harvest: the MIX kernel variants (no work counters)
+    bool mixing = o.edge_pdf && o.edge_mix > 0.0f;
+    uint32_t mterms = o.edge_mix_terms ? o.edge_mix_terms : (DR_TERM_PRIMARY | DR_TERM_SECONDARY);
+    MixArgs mx{};
+    mx.q = o.edge_pdf;
+    mx.mix = mixing ? o.edge_mix : 0.0f;
+    mx.prim = mixing && (mterms & DR_TERM_PRIMARY) ? 1 : 0;
+    mx.sec = mixing && (mterms & DR_TERM_SECONDARY) && o.max_depth >= 1 && s->tree_valid ? 1 : 0;
+    mx.estats = o.edge_stats;
+    mx.plen = s->plen.as<double>();
+    bool use_mix = mixing || o.edge_stats;
+    if (use_mix) cbase = nullptr;
+    if (o.edge_stats) k_fill<<<nblk(s->E, 256), 256, 0, st>>>(o.edge_stats, s->E, 0.0f);
+    if (mx.prim || mx.sec) {
+        drStatus r = build_view_mix(s, o.edge_pdf, o.edge_mix, mx.prim != 0, mx.sec != 0, st);
+        if (r != DR_SUCCESS) return r;
+        mx.mcdf = s->mcdf.as<double>();
+        mx.qcdf = s->qcdf.as<double>();
+    }
     if ((terms & DR_TERM_PRIMARY) && s->E > 0) {
         EvScope ev(s, 1, st);
         a.counters = cbase ? cbase + 8 : nullptr;
         dim3 g(nblk(a.M, BS)), b(BS);
         const PEdge* pe = s->pe.as<PEdge>();
         const double* pc = s->pcdf.as<double>();
-        if (a.counters) {
-            if (sm) k_primary<32, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
-            else k_primary<kStackDepth, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
+#define DR_PRIM(S, C, X) k_primary<S, C, X><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx)
+        if (use_mix) {
+            if (sm) DR_PRIM(32, false, true);
+            else DR_PRIM(kStackDepth, false, true);
+        } else if (a.counters) {
+            if (sm) DR_PRIM(32, true, false);
+            else DR_PRIM(kStackDepth, true, false);
         } else {
-            if (sm) k_primary<32, false><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
-            else k_primary<kStackDepth, false><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc);
+            if (sm) DR_PRIM(32, false, false);
+            else DR_PRIM(kStackDepth, false, false);
         }
+#undef DR_PRIM
     }
     if (o.max_depth >= 1) {
         TreeView tv;
         tv.nodes = s->etree.as<ETNode>();
         tv.valid = (s->n1 + s->n2) > 0 && (terms & DR_TERM_SECONDARY) && s->tree_valid;
         tv.cam = cam.c;
+        tv.eleaf = s->eleaf.as<int>();
+        tv.enpar = s->enpar.as<int>();
         EvScope ev(s, 2, st);
         a.counters = cbase ? cbase + 16 : nullptr;
         dim3 g(nblk(a.M, BS)), b(BS);
-#define DR_BWD(D, S, C) k_backward<D, S, C><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc)
+#define DR_BWD(D, S, C, X) k_backward<D, S, C, X><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx)
 #define DR_BWD_D(D)                                   \
-    if (a.counters) {                                 \
-        if (sm) DR_BWD(D, 32, true);                  \
-        else DR_BWD(D, kStackDepth, true);            \
+    if (use_mix) {                                    \
+        if (sm) DR_BWD(D, 32, false, true);           \
+        else DR_BWD(D, kStackDepth, false, true);     \
+    } else if (a.counters) {                          \
+        if (sm) DR_BWD(D, 32, true, false);           \
+        else DR_BWD(D, kStackDepth, true, false);     \
     } else {                                          \
-        if (sm) DR_BWD(D, 32, false);                 \
-        else DR_BWD(D, kStackDepth, false);           \
+        if (sm) DR_BWD(D, 32, false, false);          \
+        else DR_BWD(D, kStackDepth, false, false);    \
     }
         if (o.max_depth <= 1) {
             DR_BWD_D(1)
