@@ -80,6 +80,40 @@ def cpu_baseline(cfg, threads):
                       f"{cfg.max_depth}: {units} fwd+bwd pixel samples in {dt:.1f} s (FP64, {threads} threads)"}
 
 
+def proposal_leg(threads_note=None):
+    """Learned edge proposal on the 1,000-triangle scene (direct lighting):
+    harvest per-edge boundary magnitudes over 256 seeded training views
+    (128x128, 8 spp), train the 32-64-64-1 network (600 full-batch Adam steps
+    on the GPU), then compare gradient variance x backward time of the plain
+    sampler and the 0.8/0.2 mixture on 4 held-out views (128x128, 16 spp,
+    128 seeds each), per term and for the whole gradient (d_image = 1)."""
+    import torch
+
+    from paper_1904_12228_amd import api, proposal, scenegen
+
+    cfg = scenegen.config2()
+    S = api.Scene(cfg.scene)
+    train = [c for c, _ in scenegen.orbit_views(1, 256)]
+    t0 = proposal.seconds()
+    ds = proposal.harvest(S, train, 8, 1)
+    t1 = proposal.seconds()
+    prop = proposal.EdgeProposal(scenegen.mlp_params(0))
+    loss0 = prop.loss(ds)
+    prop.train(ds, 600)
+    t2 = proposal.seconds()
+    loss1 = prop.loss(ds)
+    base = cfg.camera
+    held = [(scenegen.Camera(base.position, base.look_at, base.up, base.fov_y_deg, 128, 128), 16)]
+    held += scenegen.orbit_views(99, 3, sizes=((128, 128),), spp=(16,))
+    res = proposal.evaluate(S, prop, held, 1, list(range(128)))
+    S.close()
+    return {"workload": "1,000-triangle soup + ground + quad light, depth 1; 4 held-out views 128x128 at 16 spp, "
+                        "128 seeds per sampler; mixture 0.8 learned / 0.2 plain",
+            "metric": "gradient variance x time gain (plain / learned), higher is better",
+            "train_views": len(train), "train_rows": int(ds.x.shape[0]), "harvest_s": t1 - t0, "train_s": t2 - t1,
+            "train_loss": [loss0, loss1], "per_term": res, "gain_total": res["total"]["gain"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +121,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal variance x time leg")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one plain device copy of 256 MiB (reference for HBM byte counters)")
@@ -167,7 +202,7 @@ def main():
         "counts_per_step": counts,
     }
     out = {
-        "metric": "fwd+bwd samples/s at 512^2 64spp",
+        "metric": "fwd+bwd samples/s at 512^2 64spp; grad variance x time, learned vs plain edge pdf",
         "value": value,
         "unit": "samples/s",
         "n_gpus": 1,
@@ -189,6 +224,9 @@ def main():
                      "algorithmic_bytes_per_launch": bwd_bytes},
         "kernels": kernels,
     }
+    if not args.no_proposal:
+        print("running the learned-proposal leg", file=sys.stderr, flush=True)
+        out["proposal"] = proposal_leg()
     if not args.no_cpu_baseline:
         print("running the CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_threads)

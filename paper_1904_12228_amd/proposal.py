@@ -171,3 +171,26 @@ def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=No
 def seconds() -> float:
     torch.cuda.synchronize()
     return time.perf_counter()
+
+
+def evaluate(scene: api.Scene, prop: EdgeProposal, views, depth, seeds, mix=0.8, d_image=1.0) -> dict:
+    """Gradient variance x time of the plain sampler and of the learned
+    mixture on the given views [(Camera, spp)], per term of the estimator
+    (primary edges, secondary edges) and for the whole gradient. Variances
+    are summed over views; times are the mean drRenderBackward durations."""
+    out = {}
+    for name, terms, mterms in (("primary", 2, 2), ("secondary", 4, 4), ("total", 0, 6)):
+        vp = vm = tp = tm = 0.0
+        for i, (cam, spp) in enumerate(views):
+            q = prop.propose(scene, cam)
+            a, _, ta = gradient_variance_time(scene, cam, spp, depth, [s + 10007 * i for s in seeds], terms=terms,
+                                              d_image=d_image)
+            b, _, tb = gradient_variance_time(scene, cam, spp, depth, [s + 10007 * i + 5003 for s in seeds],
+                                              edge_pdf=q, mix=mix, mix_terms=mterms, terms=terms, d_image=d_image)
+            vp += a
+            vm += b
+            tp += ta / len(views)
+            tm += tb / len(views)
+        out[name] = {"var_plain": vp, "var_learned": vm, "ms_plain": tp, "ms_learned": tm,
+                     "gain": (vp * tp) / (vm * tm) if vm * tm > 0 else float("nan")}
+    return out

@@ -446,3 +446,30 @@ def mlp_inputs(seed: int, n: int) -> np.ndarray:
     x = np.zeros((n, 32), np.float32)
     x[:, :29] = rng.normal(0.0, 1.0, (n, 29))
     return x
+
+
+# ---------------------------------------------------------------------------
+# many views of one scene (training views of the edge proposal, batched
+# inverse rendering)
+# ---------------------------------------------------------------------------
+def orbit_views(seed: int, n: int, center=(0.5, 0.4, 0.5), radius=(2.0, 2.8), elevation_deg=(10.0, 45.0),
+                fov_deg=(40.0, 50.0), sizes=((128, 128),), spp=(8,)) -> list:
+    """n seeded cameras on a spherical shell around `center` (azimuth uniform,
+    elevation and distance uniform in the given ranges), each looking at the
+    centre jittered by up to 0.1, with a size and a sample count drawn from the
+    given lists. Returns [(Camera, spp)]."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    c = np.asarray(center, np.float64)
+    out = []
+    for _ in range(n):
+        az = rng.uniform(0.0, 2.0 * np.pi)
+        el = np.radians(rng.uniform(*elevation_deg))
+        r = rng.uniform(*radius)
+        pos = c + r * np.array([np.cos(el) * np.sin(az), np.sin(el), -np.cos(el) * np.cos(az)])
+        look = c + rng.uniform(-0.1, 0.1, 3)
+        w, h = sizes[int(rng.integers(len(sizes)))]
+        s = int(spp[int(rng.integers(len(spp)))])
+        cam = Camera(tuple(float(v) for v in pos), tuple(float(v) for v in look), (0.0, 1.0, 0.0),
+                     float(rng.uniform(*fov_deg)), int(w), int(h))
+        out.append((cam, s))
+    return out
