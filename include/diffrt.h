@@ -135,6 +135,58 @@ drStatus drRenderBackward(drScene scene, const drCamera* camera, const drRenderO
                           const float* d_image, float* d_vertices, float* d_albedo, float* d_camera,
                           hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches of views and capturable optimisation steps. The thesis renders
+ * several views of one scene inside an optimisation loop (Ch. 5, Results:
+ * inverse rendering with Adam); a batch renders and differentiates many
+ * views with their own image sizes and sample counts in one kernel launch
+ * per pass, and its refit path (drSceneRefit + drBatchRefit) refreshes all
+ * geometry-dependent data with kernel launches only (no host
+ * synchronisation, no allocation), so update -> refit -> render -> loss ->
+ * backward -> Adam can be captured once in a HIP graph and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct drBatch_t* drBatch;
+
+/* Vertex update for optimisation loops: new positions ([V][3] device),
+ * triangle records, edge kinds, light sampling tables and BVH bounds over the
+ * existing BVH topology (the scene's scale constants, used for ray offsets,
+ * keep their creation values). Kernel launches only: capturable. */
+drStatus drSceneRefit(drScene scene, const float* vertices, hipStream_t stream);
+
+/* Creates a batch of n views of `scene` (which must outlive it): cameras[n]
+ * and options[n] (host arrays, copied; all views share max_depth; unit_mask,
+ * edge_pdf and edge_stats must be NULL and edge_mix 0), images[n] and
+ * d_images[n] (host arrays of device pointers, each [H][W] of its view's
+ * window, owned by the caller and used by every later call). Builds each
+ * view's primary edge table and edge hierarchy; synchronises `stream`. */
+drStatus drBatchCreate(drBatch* out, drScene scene, int32_t n, const drCamera* cameras,
+                       const drRenderOptions* options, float* const* images, const float* const* d_images,
+                       hipStream_t stream);
+
+/* Per-view tables from the scene's current vertices (after drSceneRefit),
+ * keeping each hierarchy's topology. Capturable. */
+drStatus drBatchRefit(drBatch batch, hipStream_t stream);
+
+/* Adds 1 to every view's Philox key (new random numbers for the next
+ * forward/backward pair). Capturable. */
+drStatus drBatchAdvanceSeed(drBatch batch, hipStream_t stream);
+
+/* Renders every view into its image (one launch for all views). Capturable. */
+drStatus drBatchForward(drBatch batch, hipStream_t stream);
+
+/* Gradients of sum over views of <d_image_v, image_v>: d_vertices[V][3] and
+ * d_albedo[T] (summed over views; NULL = not wanted), d_cameras[n][9] or
+ * NULL. Reads each view's d_image buffer. Needs the forward pass of the same
+ * seed. Capturable. */
+drStatus drBatchBackward(drBatch batch, float* d_vertices, float* d_albedo, float* d_cameras, hipStream_t stream);
+
+/* Launch shape (autotuning): ctas = 0 launches one workgroup per work item;
+ * ctas > 0 launches at most ctas persistent workgroups that take work items
+ * from an atomic counter. chunk = 64-unit blocks per work item (1..64). */
+drStatus drBatchSetLaunch(drBatch batch, int32_t ctas, int32_t chunk);
+
+drStatus drBatchDestroy(drBatch batch);
+
 /* One Adam step (Kingma and Ba, with bias correction) on n FP32 parameters,
  * all device arrays of length n: x -= lr * mhat / (sqrt(vhat) + eps), with
  * m, v updated in place; `step` counts from 1. Used by inverse-rendering
@@ -183,6 +235,12 @@ drStatus drMlpSoftmaxXent(const float* logits, const float* target, const int32_
  * w.r.t. theta (BF16 rounding passes gradients through unchanged). */
 drStatus drMlpBackward(const float* theta, const float* x, int32_t n, const float* d_logits, float* grad,
                        hipStream_t stream);
+
+/* drAdamStep with the step count in device memory (*step = steps taken so
+ * far, int64, incremented by this call): for optimisation steps captured in a
+ * HIP graph, whose launch arguments are fixed at capture. */
+drStatus drAdamStepCounted(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1,
+                           float beta2, float eps, int64_t* step, hipStream_t stream);
 
 /* Measurement support (not needed for rendering). With `events` on, every
  * forward, primary-edge and path-backward kernel launch is bracketed by HIP

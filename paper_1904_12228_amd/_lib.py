@@ -20,7 +20,9 @@ DR_TERM_ALL = 7
 # every entry point declared in include/diffrt.h
 EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneGetInfo", "drRender", "drRenderBackward",
            "drAdamStep", "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy",
-           "drGetErrorString", "drEdgeFeatures", "drMlpForward", "drMlpSoftmaxXent", "drMlpBackward"]
+           "drGetErrorString", "drEdgeFeatures", "drMlpForward", "drMlpSoftmaxXent", "drMlpBackward",
+           "drSceneRefit", "drBatchCreate", "drBatchRefit", "drBatchAdvanceSeed", "drBatchForward", "drBatchBackward",
+           "drBatchSetLaunch", "drBatchDestroy", "drAdamStepCounted"]
 
 MLP_PARAMS = 6337
 EDGE_FEATURES = 32
@@ -83,7 +85,22 @@ def load():
         "drGetLastDeviceError": [vp],
         "drSceneDestroy": [vp],
         "drGetErrorString": [C.c_int],
+        "drEdgeFeatures": [vp, C.POINTER(Camera), vp, vp],
+        "drMlpForward": [vp, vp, i32, vp, vp],
+        "drMlpSoftmaxXent": [vp, vp, vp, i32, vp, vp, vp, vp, vp],
+        "drMlpBackward": [vp, vp, i32, vp, vp, vp],
+        "drSceneRefit": [vp, vp, vp],
+        "drBatchCreate": [C.POINTER(vp), vp, i32, C.POINTER(Camera), C.POINTER(RenderOptions), C.POINTER(vp),
+                          C.POINTER(vp), vp],
+        "drBatchRefit": [vp, vp],
+        "drBatchAdvanceSeed": [vp, vp],
+        "drBatchForward": [vp, vp],
+        "drBatchBackward": [vp, vp, vp, vp, vp],
+        "drBatchSetLaunch": [vp, i32, i32],
+        "drBatchDestroy": [vp],
+        "drAdamStepCounted": [vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, vp, vp],
     }
+    assert set(sig) == set(EXPORTS), sorted(set(EXPORTS) ^ set(sig))
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args

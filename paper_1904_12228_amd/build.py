@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdiffrt.so")
-SOURCES = ["dr_api.hip", "dr_build.hip", "dr_render.hip", "dr_optim.hip", "dr_mlp.hip"]
+SOURCES = ["dr_api.hip", "dr_build.hip", "dr_render.hip", "dr_optim.hip", "dr_mlp.hip", "dr_batch.hip"]
 ARCH = os.environ.get("DIFFRT_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -31,7 +31,7 @@ SceneView drScene_t::view() const {
     v.ekind = ekind.as<uint8_t>();
     v.lights = lights.as<int>();
     v.lcdf = lcdf.as<double>();
-    v.atot = atot;
+    v.atot = scal.as<float>() + 12;
     v.diag = diag;
     v.tmin = tmin;
     v.two_sided = two_sided;
@@ -56,7 +56,7 @@ static void release_all(drScene_t* s) {
     s->evs.clear();
 }
 
-static bool valid_camera(const drCamera* c) {
+bool valid_camera(const drCamera* c) {
     if (!c || c->width <= 0 || c->height <= 0 || !(c->fov_y_deg > 0.0f && c->fov_y_deg < 180.0f) || !(c->near_clip > 0.0f))
         return false;
     bool full = c->window[0] == 0 && c->window[1] == 0 && c->window[2] == 0 && c->window[3] == 0;
@@ -67,13 +67,13 @@ static bool valid_camera(const drCamera* c) {
     return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0.0f;
 }
 
-static bool valid_options(const drRenderOptions* o) {
+bool valid_options(const drRenderOptions* o) {
     return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0 &&
            o->edge_mix >= 0.0f && o->edge_mix < 1.0f &&
            (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) == 0;
 }
 
-static ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {
+ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {
     ViewKey k{};
     for (int i = 0; i < 3; ++i) {
         k.cam[i] = c.position[i];

@@ -1,0 +1,57 @@
+// Launch arguments of the path kernels, shared by the single-view entry
+// points and the multi-view batches.
+#pragma once
+#include <cstdint>
+
+#include "dr_common.h"
+
+namespace dr {
+
+constexpr int BS = 64;   // one wave per block
+
+struct RenderArgs {
+    int spp, depth, M, Ww;
+    int debug_unit;    // unit whose secondary samples are printed (-1: none)
+    unsigned long long* counters;   // [5] work counters, or null
+    uint32_t k0, k1, view, terms;
+    const uint8_t* mask;
+    int* ck_tri;       // [2][M]
+    float* ck_x;       // [2][M][3]
+    uint8_t* ck_vis;   // [M]
+};
+
+// Learned-proposal mixture and harvest (the <.., MIX = true> kernel variants).
+struct MixArgs {
+    const float* q;          // [E] proposal distribution over edges
+    const double* mcdf;      // [E + 1] mixture CDF of primary edges (total weight at [E])
+    const double* qcdf;      // [E + 1] CDF of q
+    const double* plen;      // [E] clipped screen length of primary edges
+    float mix;               // weight of q
+    int prim, sec;           // mixture on for primary / secondary edges
+    float* estats;           // [E] harvest accumulator, or null
+};
+
+// Everything one view of a batch needs on the device (fixed when the batch
+// is created; buffers belong to the batch or, for images, to the caller).
+struct BatchView {
+    Cam k;
+    RenderArgs a;
+    TreeView tv;
+    const PEdge* pe;         // [E] primary edge table
+    const double* pcdf;      // [E + 1] its CDF (total at [E])
+    float* image;            // [H][W] of the window
+    const float* d_image;    // [H][W]
+    float* camacc;           // [12]
+    int reduce;              // spp divides 64: in-wave image reduction
+};
+
+// Work list of a batched launch: blocks of 64 units, view after view.
+struct BatchLaunch {
+    const BatchView* views;
+    const int* boff;         // [n + 1] first block of each view
+    int nviews, total;       // total blocks
+    int chunk;               // blocks per work item
+    int* queue;              // work-item counter of a persistent launch, or null
+};
+
+}  // namespace dr

@@ -580,6 +580,11 @@ __global__ void k_etree_parents(const ETNode* __restrict__ nodes, int nnodes, in
     }
 }
 
+__global__ void k_copy_f32(const float* __restrict__ a, int n, float* __restrict__ b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
 __global__ void k_mix_weights(const double* __restrict__ plen, const double* __restrict__ ptot, const float* __restrict__ q,
                               double mix, int E, double* __restrict__ w) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -657,9 +662,9 @@ drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool
     DR_ALLOC(s->etree, sizeof(ETNode) * nnodes);
     DR_ALLOC(s->ecode, sizeof(uint32_t) * E);
     DR_ALLOC(s->ecode_s, sizeof(uint32_t) * E);
-    DR_ALLOC(s->elist_s, sizeof(int) * E);
+    DR_ALLOC(s->elist_s, sizeof(int) * 2 * E);      // per hierarchy: sorted leaves (kept for refits)
     DR_ALLOC(s->ekeys, sizeof(uint64_t) * E);
-    DR_ALLOC(s->eparent, sizeof(int) * 2 * E);
+    DR_ALLOC(s->eparent, sizeof(int) * 4 * E);      // per hierarchy: parent links of 2m - 1 nodes
     DR_ALLOC(s->ecounter, sizeof(int2) * E);
     DR_ALLOC(s->ebounds, sizeof(double) * 6);
     DR_ALLOC(s->edepth, sizeof(int));
@@ -668,26 +673,29 @@ drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool
     int base = 1;
     for (int h = 0; h < 2; ++h) {
         int m = n[h];
+        s->tree_m[h] = m;
+        s->tree_base[h] = base;
         if (m == 0) continue;
         const int* list = h == 0 ? l1 : l2;
+        int* list_s = s->elist_s.as<int>() + (size_t)h * E;
+        int* parent = s->eparent.as<int>() + (size_t)h * 2 * E;
         k_emid_bounds<<<1, 256, 0, st>>>(s->P.as<float>(), s->edges.as<int4>(), list, m, s->ebounds.as<double>());
         k_emorton<<<blocks(m, BS), BS, 0, st>>>(s->P.as<float>(), s->edges.as<int4>(), list, m, s->ebounds.as<double>(),
                                                 s->ecode.as<uint32_t>());
         size_t stmp = 0;
         DR_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, stmp, s->ecode.as<uint32_t>(), s->ecode_s.as<uint32_t>(), list,
-                                                    s->elist_s.as<int>(), m, 0, 30, st));
+                                                    list_s, m, 0, 30, st));
         DR_ALLOC(s->sort_tmp, stmp);
         DR_CHECK(hipcub::DeviceRadixSort::SortPairs(s->sort_tmp.p, stmp, s->ecode.as<uint32_t>(), s->ecode_s.as<uint32_t>(),
-                                                    list, s->elist_s.as<int>(), m, 0, 30, st));
+                                                    list, list_s, m, 0, 30, st));
         if (m > 1) {
             k_keys64<<<blocks(m, BS), BS, 0, st>>>(s->ecode_s.as<uint32_t>(), m, s->ekeys.as<uint64_t>());
-            k_karras<<<blocks(m - 1, BS), BS, 0, st>>>(s->ekeys.as<uint64_t>(), m, s->ecounter.as<int2>(),
-                                                       s->eparent.as<int>());
-            k_etree_links<<<blocks(m - 1, BS), BS, 0, st>>>(s->ecounter.as<int2>(), m, base, h, s->elist_s.as<int>(),
+            k_karras<<<blocks(m - 1, BS), BS, 0, st>>>(s->ekeys.as<uint64_t>(), m, s->ecounter.as<int2>(), parent);
+            k_etree_links<<<blocks(m - 1, BS), BS, 0, st>>>(s->ecounter.as<int2>(), m, base, h, list_s,
                                                             s->etree.as<ETNode>(), s->ecode.as<int>());
         }
-        k_etree_refit<<<blocks(m, BS), BS, 0, st>>>(sv, cam.c, m, base, h, h, s->elist_s.as<int>(), s->eparent.as<int>(),
-                                                    s->etree.as<ETNode>(), s->ecode.as<int>(), s->edepth.as<int>());
+        k_etree_refit<<<blocks(m, BS), BS, 0, st>>>(sv, cam.c, m, base, h, h, list_s, parent, s->etree.as<ETNode>(),
+                                                    s->ecode.as<int>(), s->edepth.as<int>());
         base += std::max(m - 1, 0);
     }
     s->etree_nodes = nnodes;
@@ -699,6 +707,59 @@ drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool
     s->tree_key = key;
     s->tree_valid = true;
     return DR_SUCCESS;
+}
+
+// Per-view tables again from the current geometry, with the hierarchy's
+// topology kept (leaf order and parent links from the last build): primary
+// edge table and CDF, then the hierarchy's bounds bottom-up. Kernel launches
+// only (no host synchronisation, no allocation). counter: m - 1 ints of scratch.
+drStatus refit_view(drScene_t* s, const Cam& cam, PEdge* pe, double* plen, double* pcdf, ETNode* nodes,
+                    const int* list_s, const int* parent, const int m[2], const int base[2], int* counter, int* depth,
+                    void* scan_tmp, size_t scan_bytes, hipStream_t st) {
+    const int BS = 256;
+    int E = s->E;
+    if (E == 0) return DR_SUCCESS;
+    SceneView sv = s->view();
+    k_pedge<<<blocks(E, BS), BS, 0, st>>>(sv, cam, pe, plen);
+    DR_CHECK(hipcub::DeviceScan::InclusiveSum(scan_tmp, scan_bytes, plen, pcdf, E, st));
+    k_store_total<<<1, 1, 0, st>>>(pcdf, E, pcdf + E);
+    k_normalize_cdf<<<blocks(E, BS), BS, 0, st>>>(pcdf, E);
+    if (!nodes) return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+    for (int h = 0; h < 2; ++h) {
+        int mh = m[h];
+        if (mh == 0) continue;
+        if (mh > 1) k_fill_int<<<blocks(mh - 1, BS), BS, 0, st>>>(counter, mh - 1, 0);
+        k_etree_refit<<<blocks(mh, BS), BS, 0, st>>>(sv, cam.c, mh, base[h], h, h, list_s + (size_t)h * E,
+                                                     parent + (size_t)h * 2 * E, nodes, counter, depth);
+    }
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+size_t refit_scan_bytes(int E) {
+    size_t tmp = 0;
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (double*)nullptr, (double*)nullptr, E, (hipStream_t)0);
+    return tmp + 256;
+}
+
+// Vertex update without topology changes: triangle records, edge kinds,
+// light CDF and area, BVH bounds over the existing tree. Kernel launches only.
+drStatus refit_scene(drScene_t* s, const float* vertices, hipStream_t st) {
+    const int BS = 256;
+    int T = s->T, V = s->V;
+    k_copy_f32<<<blocks(3 * V, BS), BS, 0, st>>>(vertices, 3 * V, s->P.as<float>());
+    k_edge_kind<<<blocks(s->E, BS), BS, 0, st>>>(s->edges.as<int4>(), s->E, s->P.as<float>(), s->I.as<int>(),
+                                                 s->alb.as<float>(), s->emi.as<float>(), s->smooth ? 1 : 0,
+                                                 s->ekind.as<uint8_t>());
+    if (s->L > 0)
+        k_light_cdf<<<1, 64, 0, st>>>(s->lights.as<int>(), s->L, s->P.as<float>(), s->I.as<int>(), s->lcdf.as<double>(),
+                                      s->scal.as<float>());
+    k_tri_prep<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->tri.as<float4>());
+    if (T > 1) {
+        k_fill_int<<<blocks(T - 1, BS), BS, 0, st>>>(s->ids.as<int>(), T - 1, 0);
+        k_bvh_refit<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->ids_s.as<int>(),
+                                                  s->parent.as<int>(), s->bvh.as<BvhNode>(), s->ids.as<int>());
+    }
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 
 // Mixture of the primary edge pdf with the proposal q (weights, FP64 scan,

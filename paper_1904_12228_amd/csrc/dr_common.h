@@ -110,7 +110,7 @@ struct SceneView {
     const uint8_t* ekind;    // [E] 0 never, 1 always, 2 silhouette-only
     const int* lights;       // [L]
     const double* lcdf;      // [L]
-    float atot;              // total light area
+    const float* atot;       // total light area (device; updated by vertex refits)
     float diag, tmin;
     int two_sided;
     float background;

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/diffrt.h"
+#include "dr_args.h"
 #include "dr_common.h"
 
 namespace dr {
@@ -63,6 +64,7 @@ struct drScene_t {
         ebounds, edepth;
     int n1 = 0, n2 = 0;
     int etree_nodes = 0;
+    int tree_m[2] = {0, 0}, tree_base[2] = {0, 0};   // leaves and first node of H1 / H2
     // learned-proposal mixture: weights, mixture CDF of primary edges, CDF of
     // the proposal; edge-tree parent links (node << 1 | side)
     dr::Buf mixw, mcdf, qcdf, eleaf, enpar;
@@ -92,11 +94,26 @@ namespace dr {
 drStatus build_scene_static(drScene_t* s, hipStream_t st);   // kinds, lights, triangles, BVH
 drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool need_tree, hipStream_t st);
 drStatus build_view_mix(drScene_t* s, const float* q, float mix, bool primary, bool secondary, hipStream_t st);
+drStatus refit_view(drScene_t* s, const Cam& cam, PEdge* pe, double* plen, double* pcdf, ETNode* nodes,
+                    const int* list_s, const int* parent, const int m[2], const int base[2], int* counter, int* depth,
+                    void* scan_tmp, size_t scan_bytes, hipStream_t st);
+size_t refit_scan_bytes(int E);
+drStatus refit_scene(drScene_t* s, const float* vertices, hipStream_t st);
 Cam make_cam(const drCamera& c);
 
 // dr_render.hip
 drStatus launch_forward(drScene_t* s, const Cam& cam, const drRenderOptions& o, float* image, hipStream_t st);
 drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o, const float* d_image,
                          float* d_vertices, float* d_albedo, float* d_camera, hipStream_t st);
+RenderArgs render_args(drScene_t* s, const Cam& cam, const drRenderOptions& o);
+drStatus launch_batch_forward(drScene_t* s, BatchLaunch L, int ctas, int max_pixels, hipStream_t st);
+drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth, float* dV, float* dA, float* d_cameras,
+                               hipStream_t st);
+drStatus launch_batch_seed(BatchView* views, int n, uint32_t add, hipStream_t st);
 
 }  // namespace dr
+
+// dr_api.hip: argument checks and the per-view cache key
+dr::ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o);
+bool valid_camera(const drCamera* c);
+bool valid_options(const drRenderOptions* o);

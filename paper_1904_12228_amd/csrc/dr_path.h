@@ -90,7 +90,7 @@ __device__ inline NeeSample nee_sample(const SceneView& s, float4 u, v3 x, v3 ns
     q.w = wh;
     q.r = r;
     if (cp <= 0.0f || cy <= 0.0f) return q;
-    q.K = s.emi[lt] * cy / r2 * s.atot / kPi;
+    q.K = s.emi[lt] * cy / r2 * s.atot[0] / kPi;
     return q;
 }
 

@@ -14,34 +14,11 @@
 #include <cstdlib>
 #include <type_traits>
 
+#include "dr_args.h"
 #include "dr_host.h"
 #include "dr_path.h"
 
 namespace dr {
-
-constexpr int BS = 64;
-
-struct RenderArgs {
-    int spp, depth, M, Ww;
-    int debug_unit;    // unit whose secondary samples are printed (-1: none)
-    unsigned long long* counters;   // [5] work counters, or null
-    uint32_t k0, k1, view, terms;
-    const uint8_t* mask;
-    int* ck_tri;       // [2][M]
-    float* ck_x;       // [2][M][3]
-    uint8_t* ck_vis;   // [M]
-};
-
-// Learned-proposal mixture and harvest (the <.., MIX = true> kernel variants).
-struct MixArgs {
-    const float* q;          // [E] proposal distribution over edges
-    const double* mcdf;      // [E + 1] mixture CDF of primary edges (total weight at [E])
-    const double* qcdf;      // [E + 1] CDF of q
-    const double* plen;      // [E] clipped screen length of primary edges
-    float mix;               // weight of q
-    int prim, sec;           // mixture on for primary / secondary edges
-    float* estats;           // [E] harvest accumulator, or null
-};
 
 __device__ inline void unit_pixel(const Cam& k, const RenderArgs& a, int m, int& pix, int& px, int& py, uint32_t& sid) {
     pix = m / a.spp;
@@ -67,12 +44,14 @@ __device__ inline void flush_work(const Work& w, unsigned long long* c) {
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
+// One wave of units [mbase, mbase + 64) of one view; stk: the block's LDS
+// traversal stacks.
 template <int STK, bool CNT>
-__global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a, float* __restrict__ image, int reduce) {
-    __shared__ int stk[STK * BS];
+__device__ __forceinline__ void forward_body(const SceneView& s, const Cam& k, const RenderArgs& a, float* __restrict__ image,
+                                             int reduce, int mbase, int* stk) {
     int lane = threadIdx.x;
     int* my = stk + lane;
-    int m = blockIdx.x * BS + lane;
+    int m = mbase + lane;
     float L = 0.0f;
     int pix = 0;
     typename std::conditional<CNT, Work, NoWork>::type wk;
@@ -144,6 +123,12 @@ __global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a
     } else if (m < a.M) {
         atomicAdd(&image[pix], v);
     }
+}
+
+template <int STK, bool CNT>
+__global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a, float* __restrict__ image, int reduce) {
+    __shared__ int stk[STK * BS];
+    forward_body<STK, CNT>(s, k, a, image, reduce, blockIdx.x * BS, stk);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,13 +283,13 @@ __device__ inline void flush_cam(const CamAcc& ca, float* camacc) {
 // primary edge samples (eq. mc): one per unit
 // ---------------------------------------------------------------------------
 template <int STK, bool CNT, bool MIX>
-__global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
-                                                const double* __restrict__ cdf, const float* __restrict__ d_image,
-                                                float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
-    __shared__ int stk[STK * BS];
+__device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, const RenderArgs& a, const PEdge* __restrict__ pe,
+                                             const double* __restrict__ cdf, const float* __restrict__ d_image,
+                                             float* __restrict__ dV, float* __restrict__ camacc, const MixArgs& mx,
+                                             int mbase, int* stk) {
     int lane = threadIdx.x;
     int* my = stk + lane;
-    int m = blockIdx.x * BS + lane;
+    int m = mbase + lane;
     CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     typename std::conditional<CNT, Work, NoWork>::type wk;
     double total = cdf[s.E];
@@ -382,6 +367,14 @@ __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a
     });
     flush_work(wk, a.counters);
     flush_cam(ca, camacc);
+}
+
+template <int STK, bool CNT, bool MIX>
+__global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
+                                                const double* __restrict__ cdf, const float* __restrict__ d_image,
+                                                float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
+    __shared__ int stk[STK * BS];
+    primary_body<STK, CNT, MIX>(s, k, a, pe, cdf, d_image, dV, camacc, mx, blockIdx.x * BS, stk);
 }
 
 // ---------------------------------------------------------------------------
@@ -537,13 +530,13 @@ __device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int 
 // backward over paths: secondary edges at every vertex + interior adjoint
 // ---------------------------------------------------------------------------
 template <int MAXD, int STK, bool CNT, bool MIX>
-__global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs a, TreeView tv, const float* __restrict__ d_image,
-                                                 float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc,
-                                                 MixArgs mx) {
-    __shared__ int stk[STK * BS];
+__device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, const RenderArgs& a, const TreeView& tv,
+                                              const float* __restrict__ d_image, float* __restrict__ dV,
+                                              float* __restrict__ dA, float* __restrict__ camacc, const MixArgs& mx,
+                                              int mbase, int* stk) {
     int lane = threadIdx.x;
     int* my = stk + lane;
-    int m = blockIdx.x * BS + lane;
+    int m = mbase + lane;
     CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     typename std::conditional<CNT, Work, NoWork>::type wk;
     bool have0 = false;          // vertex-1 triangle gradients, scattered per wave group
@@ -749,8 +742,15 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
 }
 
 // dL/d(position, look_at, up) from the frame adjoints (f, r, u, c).
-__global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, float* __restrict__ d_camera) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+template <int MAXD, int STK, bool CNT, bool MIX>
+__global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs a, TreeView tv, const float* __restrict__ d_image,
+                                                 float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc,
+                                                 MixArgs mx) {
+    __shared__ int stk[STK * BS];
+    backward_body<MAXD, STK, CNT, MIX>(s, k, a, tv, d_image, dV, dA, camacc, mx, blockIdx.x * BS, stk);
+}
+
+__device__ inline void cam_finalize(const Cam& k, const float* __restrict__ acc, float* __restrict__ d_camera) {
     v3 gf = {acc[0], acc[1], acc[2]}, gr = {acc[3], acc[4], acc[5]}, gu = {acc[6], acc[7], acc[8]}, gc = {acc[9], acc[10], acc[11]};
     v3 look = k.look, up = k.upv;
     // u = r x f
@@ -767,6 +767,123 @@ __global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, float* __re
     d_camera[0] = gc.x; d_camera[1] = gc.y; d_camera[2] = gc.z;
     d_camera[3] = gl.x; d_camera[4] = gl.y; d_camera[5] = gl.z;
     d_camera[6] = gup.x; d_camera[7] = gup.y; d_camera[8] = gup.z;
+}
+
+__global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, float* __restrict__ d_camera) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    cam_finalize(k, acc, d_camera);
+}
+
+// ---------------------------------------------------------------------------
+// batches of views: one launch per kernel for every view. Each block of 64
+// units lies in one view, so the view's arguments are uniform per block.
+// Work items of `chunk` blocks are taken in grid order, or from an atomic
+// counter when the grid is persistent (smaller than the work list).
+// ---------------------------------------------------------------------------
+__device__ inline int batch_view(const BatchLaunch& L, int b) {
+    int lo = 0, hi = L.nviews - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (L.boff[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int batch_next(const BatchLaunch& L, int it, int* slot) {
+    int item;
+    if (L.queue) {
+        if (threadIdx.x == 0) *slot = atomicAdd(L.queue, 1);
+        __syncthreads();
+        item = *slot;
+        __syncthreads();
+    } else {
+        item = blockIdx.x + it * gridDim.x;
+    }
+    return __builtin_amdgcn_readfirstlane(item);
+}
+
+template <int STK>
+__global__ __launch_bounds__(BS) void k_forward_batch(SceneView s, BatchLaunch L) {
+    __shared__ int stk[STK * BS];
+    __shared__ int slot;
+    for (int it = 0;; ++it) {
+        int item = batch_next(L, it, &slot);
+        if (item >= (L.total + L.chunk - 1) / L.chunk) break;
+        for (int c = 0; c < L.chunk; ++c) {
+            int b = item * L.chunk + c;
+            if (b >= L.total) break;
+            int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
+            const BatchView& bv = L.views[v];
+            forward_body<STK, false>(s, bv.k, bv.a, bv.image, bv.reduce, (b - L.boff[v]) * BS, stk);
+        }
+    }
+}
+
+template <int STK>
+__global__ __launch_bounds__(BS) void k_primary_batch(SceneView s, BatchLaunch L, float* __restrict__ dV) {
+    __shared__ int stk[STK * BS];
+    __shared__ int slot;
+    MixArgs mx{};
+    for (int it = 0;; ++it) {
+        int item = batch_next(L, it, &slot);
+        if (item >= (L.total + L.chunk - 1) / L.chunk) break;
+        for (int c = 0; c < L.chunk; ++c) {
+            int b = item * L.chunk + c;
+            if (b >= L.total) break;
+            int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
+            const BatchView& bv = L.views[v];
+            primary_body<STK, false, false>(s, bv.k, bv.a, bv.pe, bv.pcdf, bv.d_image, dV, bv.camacc, mx,
+                                            (b - L.boff[v]) * BS, stk);
+        }
+    }
+}
+
+template <int MAXD, int STK>
+__global__ __launch_bounds__(BS) void k_backward_batch(SceneView s, BatchLaunch L, float* __restrict__ dV,
+                                                       float* __restrict__ dA) {
+    __shared__ int stk[STK * BS];
+    __shared__ int slot;
+    MixArgs mx{};
+    for (int it = 0;; ++it) {
+        int item = batch_next(L, it, &slot);
+        if (item >= (L.total + L.chunk - 1) / L.chunk) break;
+        for (int c = 0; c < L.chunk; ++c) {
+            int b = item * L.chunk + c;
+            if (b >= L.total) break;
+            int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
+            const BatchView& bv = L.views[v];
+            backward_body<MAXD, STK, false, false>(s, bv.k, bv.a, bv.tv, bv.d_image, dV, dA, bv.camacc, mx,
+                                                   (b - L.boff[v]) * BS, stk);
+        }
+    }
+}
+
+__global__ void k_cam_finalize_batch(const BatchView* __restrict__ views, int n, float* __restrict__ d_cameras) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) cam_finalize(views[v].k, views[v].camacc, d_cameras + 9 * v);
+}
+
+__global__ void k_batch_zero(const BatchView* __restrict__ views, int n, int image) {
+    // zeroes each view's image (image = 1) or camera accumulator (image = 0)
+    int v = blockIdx.y;
+    if (v >= n) return;
+    const BatchView& bv = views[v];
+    if (image) {
+        int npix = bv.a.M / bv.a.spp;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += gridDim.x * blockDim.x) bv.image[i] = 0.0f;
+    } else if (blockIdx.x == 0 && threadIdx.x < 12) {
+        bv.camacc[threadIdx.x] = 0.0f;
+    }
+}
+
+__global__ void k_batch_seed(BatchView* __restrict__ views, int n, uint32_t add) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) views[v].a.k0 += add;
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, int v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
 }
 
 __global__ void k_fill(float* __restrict__ p, long n, float v) {
@@ -940,5 +1057,67 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         k_cam_finalize<<<1, 1, 0, st>>>(cam, camacc, d_camera);
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
+
+static int batch_grid(const BatchLaunch& L, int ctas) {
+    int items = (L.total + L.chunk - 1) / L.chunk;
+    return ctas > 0 ? std::max(1, std::min(ctas, items)) : std::max(1, items);
+}
+
+drStatus launch_batch_forward(drScene_t* s, BatchLaunch L, int ctas, int max_pixels, hipStream_t st) {
+    SceneView sv = s->view();
+    bool sm = small_stack(s);
+    sv.stk_cap = sm ? 32 : kStackDepth;
+    dim3 zg(std::max(1, std::min((max_pixels + 255) / 256, 1024)), L.nviews);
+    k_batch_zero<<<zg, 256, 0, st>>>(L.views, L.nviews, 1);
+    if (L.total == 0) return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+    if (!(ctas > 0)) L.queue = nullptr;
+    else k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
+    int grid = batch_grid(L, ctas);
+    if (sm) k_forward_batch<32><<<grid, BS, 0, st>>>(sv, L);
+    else k_forward_batch<kStackDepth><<<grid, BS, 0, st>>>(sv, L);
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth, float* dV, float* dA, float* d_cameras,
+                               hipStream_t st) {
+    SceneView sv = s->view();
+    bool sm = small_stack(s);
+    sv.stk_cap = sm ? 32 : kStackDepth;
+    k_fill<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, 3L * s->V, 0.0f);
+    k_fill<<<nblk(s->T, 256), 256, 0, st>>>(dA, s->T, 0.0f);
+    k_batch_zero<<<dim3(1, L.nviews), 64, 0, st>>>(L.views, L.nviews, 0);
+    if (L.total > 0) {
+        if (!(ctas > 0)) L.queue = nullptr;
+        int grid = batch_grid(L, ctas);
+        if (s->E > 0) {
+            if (L.queue) k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
+            if (sm) k_primary_batch<32><<<grid, BS, 0, st>>>(sv, L, dV);
+            else k_primary_batch<kStackDepth><<<grid, BS, 0, st>>>(sv, L, dV);
+        }
+        if (depth >= 1) {
+            if (L.queue) k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
+#define DR_BB(D)                                                                  \
+    if (sm) k_backward_batch<D, 32><<<grid, BS, 0, st>>>(sv, L, dV, dA);          \
+    else k_backward_batch<D, kStackDepth><<<grid, BS, 0, st>>>(sv, L, dV, dA);
+            if (depth <= 1) {
+                DR_BB(1)
+            } else if (depth <= 3) {
+                DR_BB(3)
+            } else {
+                DR_BB(6)
+            }
+#undef DR_BB
+        }
+    }
+    if (d_cameras) k_cam_finalize_batch<<<(L.nviews + 63) / 64, 64, 0, st>>>(L.views, L.nviews, d_cameras);
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+drStatus launch_batch_seed(BatchView* views, int n, uint32_t add, hipStream_t st) {
+    k_batch_seed<<<(n + 63) / 64, 64, 0, st>>>(views, n, add);
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+RenderArgs render_args(drScene_t* s, const Cam& cam, const drRenderOptions& o) { return make_args(s, cam, o); }
 
 }  // namespace dr
