@@ -1,5 +1,6 @@
 // C ABI of the gfx950 differentiable path tracer (see include/diffrt.h).
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -155,6 +156,10 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     s->smooth = d->normals != nullptr;
     s->two_sided = d->emission_two_sided ? 1 : 0;
     s->background = d->background;
+    if (const char* e = std::getenv("DIFFRT_GRAD_SHARDS")) {
+        int k = std::atoi(e);
+        if (k >= 1 && k <= 64 && (k & (k - 1)) == 0) s->grad_shards = k;
+    }
     API_CHECK(hipGetDevice(&s->device));
     auto fail = [&](drStatus e) {
         release_all(s);

@@ -18,6 +18,11 @@ struct RenderArgs {
     int* ck_tri;       // [2][M]
     float* ck_x;       // [2][M][3]
     uint8_t* ck_vis;   // [M]
+    // gradient shards: block b adds into copy (b & (gshards - 1)) of the
+    // gradient arrays (gstride floats apart) and of the camera accumulator
+    // (12 floats apart); the copies are summed after the kernels
+    int gshards;
+    long gstride;
 };
 
 // Learned-proposal mixture and harvest (the <.., MIX = true> kernel variants).
@@ -52,6 +57,8 @@ struct BatchLaunch {
     int nviews, total;       // total blocks
     int chunk;               // blocks per work item
     int* queue;              // work-item counter of a persistent launch, or null
+    int gshards;             // gradient copies (power of two): block b adds into copy b & (gshards - 1),
+    long gstride;            // gstride floats apart; each view's camera accumulator has gshards x 12 floats
 };
 
 }  // namespace dr

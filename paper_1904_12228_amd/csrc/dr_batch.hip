@@ -19,15 +19,15 @@ struct drBatch_t {
     std::vector<Cam> cams;
     std::vector<int> m0, m1, base0, base1;
     int total_blocks = 0, max_pixels = 0;
-    int ctas = 0, chunk = 1;
+    int ctas = 0, chunk = 1, shards = 1;
     size_t scan_bytes = 0;
     Buf ck_tri, ck_x, ck_vis, pe, pcdf, eleaf, elist, eparent, camacc, views, boff, queue, plen, counter, depth_scr,
-        scan_tmp, dv_scr, da_scr;
+        scan_tmp, dv_scr;   // dv_scr: gradient copies [shards][3V + T]
     std::vector<Buf> etree, enpar;
 
     void release() {
         for (Buf* b : {&ck_tri, &ck_x, &ck_vis, &pe, &pcdf, &eleaf, &elist, &eparent, &camacc, &views, &boff, &queue, &plen,
-                       &counter, &depth_scr, &scan_tmp, &dv_scr, &da_scr})
+                       &counter, &depth_scr, &scan_tmp, &dv_scr})
             b->release();
         for (auto& b : etree) b.release();
         for (auto& b : enpar) b.release();
@@ -88,7 +88,8 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
     B_ALLOC(b->eleaf, sizeof(int) * (size_t)n * E);
     B_ALLOC(b->elist, sizeof(int) * (size_t)n * 2 * E);
     B_ALLOC(b->eparent, sizeof(int) * (size_t)n * 4 * E);
-    B_ALLOC(b->camacc, sizeof(float) * 12 * (size_t)n);
+    b->shards = s->grad_shards;
+    B_ALLOC(b->camacc, sizeof(float) * 12 * (size_t)n * b->shards);
     B_ALLOC(b->views, sizeof(BatchView) * (size_t)n);
     B_ALLOC(b->boff, sizeof(int) * (size_t)(n + 1));
     B_ALLOC(b->queue, sizeof(int));
@@ -97,8 +98,7 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
     B_ALLOC(b->depth_scr, sizeof(int));
     b->scan_bytes = refit_scan_bytes(std::max(E, 1));
     B_ALLOC(b->scan_tmp, b->scan_bytes);
-    B_ALLOC(b->dv_scr, sizeof(float) * 3 * (size_t)s->V);
-    B_ALLOC(b->da_scr, sizeof(float) * (size_t)s->T);
+    B_ALLOC(b->dv_scr, sizeof(float) * (size_t)b->shards * (3 * (size_t)s->V + s->T));
     b->etree.resize(n);
     b->enpar.resize(n);
     std::vector<BatchView> hv(n);
@@ -152,7 +152,7 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
         bv.pcdf = pcdf_v;
         bv.image = images[v];
         bv.d_image = d_images[v];
-        bv.camacc = b->camacc.as<float>() + 12 * v;
+        bv.camacc = b->camacc.as<float>() + 12 * (size_t)v * b->shards;
         bv.reduce = (BS % opts[v].spp) == 0 ? 1 : 0;
     }
     s->tree_valid = false;
@@ -171,6 +171,8 @@ static BatchLaunch batch_launch(drBatch_t* b) {
     L.total = b->total_blocks;
     L.chunk = b->chunk;
     L.queue = b->queue.as<int>();
+    L.gshards = b->shards;
+    L.gstride = 3L * b->s->V + b->s->T;
     return L;
 }
 
@@ -190,9 +192,8 @@ extern "C" drStatus drBatchForward(drBatch b, hipStream_t st) {
 
 extern "C" drStatus drBatchBackward(drBatch b, float* d_vertices, float* d_albedo, float* d_cameras, hipStream_t st) {
     if (!b) return DR_ERROR_INVALID_VALUE;
-    float* dV = d_vertices ? d_vertices : b->dv_scr.as<float>();
-    float* dA = d_albedo ? d_albedo : b->da_scr.as<float>();
-    drStatus r = launch_batch_backward(b->s, batch_launch(b), b->ctas, b->depth, dV, dA, d_cameras, st);
+    drStatus r = launch_batch_backward(b->s, batch_launch(b), b->ctas, b->depth, b->dv_scr.as<float>(), d_vertices,
+                                       d_albedo, d_cameras, st);
     b->s->last_stream = st;
     return r;
 }

@@ -54,6 +54,7 @@ struct drScene_t {
     float background = 0.0f;
     float diag = 0.0f, tmin = 0.0f, atot = 0.0f;
     int bvh_depth = 0;               // internal nodes on the longest root-to-leaf path
+    int grad_shards = 16;            // copies of the gradient arrays (power of two; see launch_backward)
     uint64_t version = 0;            // bumps on every vertex update
     // scene data
     dr::Buf P, I, N, alb, emi, tri, bvh, edges, ekind, lights, lcdf, scal, err;
@@ -107,8 +108,8 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
                          float* d_vertices, float* d_albedo, float* d_camera, hipStream_t st);
 RenderArgs render_args(drScene_t* s, const Cam& cam, const drRenderOptions& o);
 drStatus launch_batch_forward(drScene_t* s, BatchLaunch L, int ctas, int max_pixels, hipStream_t st);
-drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth, float* dV, float* dA, float* d_cameras,
-                               hipStream_t st);
+drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth, float* shard, float* d_vertices,
+                               float* d_albedo, float* d_cameras, hipStream_t st);
 drStatus launch_batch_seed(BatchView* views, int n, uint32_t add, hipStream_t st);
 
 }  // namespace dr

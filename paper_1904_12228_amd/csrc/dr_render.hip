@@ -374,7 +374,8 @@ __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a
                                                 const double* __restrict__ cdf, const float* __restrict__ d_image,
                                                 float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
     __shared__ int stk[STK * BS];
-    primary_body<STK, CNT, MIX>(s, k, a, pe, cdf, d_image, dV, camacc, mx, blockIdx.x * BS, stk);
+    int sh = blockIdx.x & (a.gshards - 1);
+    primary_body<STK, CNT, MIX>(s, k, a, pe, cdf, d_image, dV + sh * a.gstride, camacc + 12 * sh, mx, blockIdx.x * BS, stk);
 }
 
 // ---------------------------------------------------------------------------
@@ -747,7 +748,9 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
                                                  float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc,
                                                  MixArgs mx) {
     __shared__ int stk[STK * BS];
-    backward_body<MAXD, STK, CNT, MIX>(s, k, a, tv, d_image, dV, dA, camacc, mx, blockIdx.x * BS, stk);
+    int sh = blockIdx.x & (a.gshards - 1);
+    backward_body<MAXD, STK, CNT, MIX>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride, camacc + 12 * sh,
+                                       mx, blockIdx.x * BS, stk);
 }
 
 __device__ inline void cam_finalize(const Cam& k, const float* __restrict__ acc, float* __restrict__ d_camera) {
@@ -769,9 +772,23 @@ __device__ inline void cam_finalize(const Cam& k, const float* __restrict__ acc,
     d_camera[6] = gup.x; d_camera[7] = gup.y; d_camera[8] = gup.z;
 }
 
-__global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, float* __restrict__ d_camera) {
+__global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, int shards, float* __restrict__ d_camera) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    cam_finalize(k, acc, d_camera);
+    float sum[12];
+    for (int i = 0; i < 12; ++i) {
+        sum[i] = 0.0f;
+        for (int h = 0; h < shards; ++h) sum[i] += acc[12 * h + i];
+    }
+    cam_finalize(k, sum, d_camera);
+}
+
+// out[i] = sum over the copies of shard[h * stride + i], i < n
+__global__ void k_reduce_shards(const float* __restrict__ shard, int shards, long stride, long n, float* __restrict__ out) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = 0.0f;
+    for (int h = 0; h < shards; ++h) v += shard[h * stride + i];
+    out[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -833,8 +850,9 @@ __global__ __launch_bounds__(BS) void k_primary_batch(SceneView s, BatchLaunch L
             if (b >= L.total) break;
             int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
             const BatchView& bv = L.views[v];
-            primary_body<STK, false, false>(s, bv.k, bv.a, bv.pe, bv.pcdf, bv.d_image, dV, bv.camacc, mx,
-                                            (b - L.boff[v]) * BS, stk);
+            int sh = blockIdx.x & (L.gshards - 1);
+            primary_body<STK, false, false>(s, bv.k, bv.a, bv.pe, bv.pcdf, bv.d_image, dV + sh * L.gstride,
+                                            bv.camacc + 12 * sh, mx, (b - L.boff[v]) * BS, stk);
         }
     }
 }
@@ -853,18 +871,26 @@ __global__ __launch_bounds__(BS) void k_backward_batch(SceneView s, BatchLaunch 
             if (b >= L.total) break;
             int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
             const BatchView& bv = L.views[v];
-            backward_body<MAXD, STK, false, false>(s, bv.k, bv.a, bv.tv, bv.d_image, dV, dA, bv.camacc, mx,
-                                                   (b - L.boff[v]) * BS, stk);
+            int sh = blockIdx.x & (L.gshards - 1);
+            backward_body<MAXD, STK, false, false>(s, bv.k, bv.a, bv.tv, bv.d_image, dV + sh * L.gstride,
+                                                   dA + sh * L.gstride, bv.camacc + 12 * sh, mx, (b - L.boff[v]) * BS,
+                                                   stk);
         }
     }
 }
 
-__global__ void k_cam_finalize_batch(const BatchView* __restrict__ views, int n, float* __restrict__ d_cameras) {
+__global__ void k_cam_finalize_batch(const BatchView* __restrict__ views, int n, int shards, float* __restrict__ d_cameras) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) cam_finalize(views[v].k, views[v].camacc, d_cameras + 9 * v);
+    if (v >= n) return;
+    float sum[12];
+    for (int i = 0; i < 12; ++i) {
+        sum[i] = 0.0f;
+        for (int h = 0; h < shards; ++h) sum[i] += views[v].camacc[12 * h + i];
+    }
+    cam_finalize(views[v].k, sum, d_cameras + 9 * v);
 }
 
-__global__ void k_batch_zero(const BatchView* __restrict__ views, int n, int image) {
+__global__ void k_batch_zero(const BatchView* __restrict__ views, int n, int image, int shards) {
     // zeroes each view's image (image = 1) or camera accumulator (image = 0)
     int v = blockIdx.y;
     if (v >= n) return;
@@ -872,8 +898,8 @@ __global__ void k_batch_zero(const BatchView* __restrict__ views, int n, int ima
     if (image) {
         int npix = bv.a.M / bv.a.spp;
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += gridDim.x * blockDim.x) bv.image[i] = 0.0f;
-    } else if (blockIdx.x == 0 && threadIdx.x < 12) {
-        bv.camacc[threadIdx.x] = 0.0f;
+    } else if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < 12 * shards; i += blockDim.x) bv.camacc[i] = 0.0f;
     }
 }
 
@@ -933,6 +959,8 @@ static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions&
     a.ck_tri = s->ck_tri.as<int>();
     a.ck_x = s->ck_x.as<float>();
     a.ck_vis = s->ck_vis.as<uint8_t>();
+    a.gshards = 1;
+    a.gstride = 0;
     return a;
 }
 
@@ -969,18 +997,19 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
     SceneView sv = s->view();
     bool sm = small_stack(s);
     sv.stk_cap = sm ? 32 : kStackDepth;
-    float* dV = d_vertices;
-    float* dA = d_albedo;
-    // outputs the caller did not ask for go to scratch
-    size_t need = sizeof(float) * (3 * (size_t)s->V + s->T + 12);
+    // gradients accumulate into `shards` copies (layout per copy: dV [3V] then
+    // dA [T]), camera accumulators into `shards` x 12 floats; the copies are
+    // summed into the caller's arrays at the end
+    int shards = s->grad_shards;
+    long stride = 3L * s->V + s->T;
+    size_t need = sizeof(float) * (size_t)shards * (stride + 12);
     if (s->camacc.ensure(need) != hipSuccess) return DR_ERROR_OUT_OF_MEMORY;
-    float* scratch = s->camacc.as<float>();
-    float* camacc = scratch;
-    if (!dV) dV = scratch + 12;
-    if (!dA) dA = scratch + 12 + 3 * (size_t)s->V;
-    k_fill<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, 3L * s->V, 0.0f);
-    k_fill<<<nblk(s->T, 256), 256, 0, st>>>(dA, s->T, 0.0f);
-    k_fill<<<1, 64, 0, st>>>(camacc, 12, 0.0f);
+    float* camacc = s->camacc.as<float>();
+    float* dV = camacc + 12 * (size_t)shards;
+    float* dA = dV + 3L * s->V;
+    a.gshards = shards;
+    a.gstride = stride;
+    k_fill<<<nblk((long)shards * (stride + 12), 256), 256, 0, st>>>(camacc, (long)shards * (stride + 12), 0.0f);
     uint32_t terms = a.terms;
     unsigned long long* cbase = a.counters;
     // learned-proposal mixture and harvest: the MIX kernel variants (no work counters)
@@ -1053,8 +1082,10 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
 #undef DR_BWD_D
 #undef DR_BWD
     }
+    if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, shards, stride, 3L * s->V, d_vertices);
+    if (d_albedo) k_reduce_shards<<<nblk(s->T, 256), 256, 0, st>>>(dA, shards, stride, s->T, d_albedo);
     if (d_camera)
-        k_cam_finalize<<<1, 1, 0, st>>>(cam, camacc, d_camera);
+        k_cam_finalize<<<1, 1, 0, st>>>(cam, camacc, shards, d_camera);
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 
@@ -1068,7 +1099,7 @@ drStatus launch_batch_forward(drScene_t* s, BatchLaunch L, int ctas, int max_pix
     bool sm = small_stack(s);
     sv.stk_cap = sm ? 32 : kStackDepth;
     dim3 zg(std::max(1, std::min((max_pixels + 255) / 256, 1024)), L.nviews);
-    k_batch_zero<<<zg, 256, 0, st>>>(L.views, L.nviews, 1);
+    k_batch_zero<<<zg, 256, 0, st>>>(L.views, L.nviews, 1, L.gshards);
     if (L.total == 0) return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
     if (!(ctas > 0)) L.queue = nullptr;
     else k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
@@ -1078,14 +1109,16 @@ drStatus launch_batch_forward(drScene_t* s, BatchLaunch L, int ctas, int max_pix
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 
-drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth, float* dV, float* dA, float* d_cameras,
-                               hipStream_t st) {
+drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth, float* shard, float* d_vertices,
+                               float* d_albedo, float* d_cameras, hipStream_t st) {
     SceneView sv = s->view();
     bool sm = small_stack(s);
     sv.stk_cap = sm ? 32 : kStackDepth;
-    k_fill<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, 3L * s->V, 0.0f);
-    k_fill<<<nblk(s->T, 256), 256, 0, st>>>(dA, s->T, 0.0f);
-    k_batch_zero<<<dim3(1, L.nviews), 64, 0, st>>>(L.views, L.nviews, 0);
+    // `shard`: gshards copies of [dV (3V) | dA (T)], gstride = 3V + T floats apart
+    float* dV = shard;
+    float* dA = shard + 3L * s->V;
+    k_fill<<<nblk((long)L.gshards * L.gstride, 256), 256, 0, st>>>(shard, (long)L.gshards * L.gstride, 0.0f);
+    k_batch_zero<<<dim3(1, L.nviews), 64, 0, st>>>(L.views, L.nviews, 0, L.gshards);
     if (L.total > 0) {
         if (!(ctas > 0)) L.queue = nullptr;
         int grid = batch_grid(L, ctas);
@@ -1109,7 +1142,9 @@ drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth,
 #undef DR_BB
         }
     }
-    if (d_cameras) k_cam_finalize_batch<<<(L.nviews + 63) / 64, 64, 0, st>>>(L.views, L.nviews, d_cameras);
+    if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, L.gshards, L.gstride, 3L * s->V, d_vertices);
+    if (d_albedo) k_reduce_shards<<<nblk(s->T, 256), 256, 0, st>>>(dA, L.gshards, L.gstride, s->T, d_albedo);
+    if (d_cameras) k_cam_finalize_batch<<<(L.nviews + 63) / 64, 64, 0, st>>>(L.views, L.nviews, L.gshards, d_cameras);
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 
