@@ -49,6 +49,7 @@ static void release_all(drScene_t* s) {
                    &s->ecode_s, &s->elist_s, &s->ekeys, &s->eparent, &s->ecounter, &s->etree, &s->ebounds, &s->edepth,
                    &s->ck_tri, &s->ck_x, &s->ck_vis, &s->camacc};
     for (Buf* b : bufs) b->release();
+    for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount}) b->release();
     s->counters.release();
     for (auto& e : s->evs) {
         (void)hipEventDestroy(e.a);
@@ -156,6 +157,7 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     s->smooth = d->normals != nullptr;
     s->two_sided = d->emission_two_sided ? 1 : 0;
     s->background = d->background;
+    if (const char* e = std::getenv("DIFFRT_SPLIT_BACKWARD")) s->split_backward = std::atoi(e) != 0;
     if (const char* e = std::getenv("DIFFRT_GRAD_SHARDS")) {
         int k = std::atoi(e);
         if (k >= 1 && k <= 64 && (k & (k - 1)) == 0) s->grad_shards = k;

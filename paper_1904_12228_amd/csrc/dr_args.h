@@ -36,6 +36,23 @@ struct MixArgs {
     float* estats;           // [E] harvest accumulator, or null
 };
 
+// Side-path query of the split backward: a secondary edge sample whose two
+// one-sided radiances are traced by a dense kernel of their own.
+struct SideQuery {
+    float p[3], wp[3], wm[3];    // shading point, directions just off the edge on both sides
+    uint32_t sid;                // pixel-sample id (Philox counter word)
+    int edge;
+    float pdf;
+    int k;                       // path vertex (0 = first hit)
+};
+
+struct SplitArgs {
+    SideQuery* q;                // [cap]
+    float2* res;                 // [cap] (radiance on the + side, on the - side)
+    int* qidx;                   // [MAXD][M] query of (vertex, unit), -1 if none
+    int* count;                  // queries appended
+};
+
 // Everything one view of a batch needs on the device (fixed when the batch
 // is created; buffers belong to the batch or, for images, to the caller).
 struct BatchView {

@@ -77,6 +77,9 @@ struct drScene_t {
     bool ck_valid = false;
     // camera adjoint accumulator (f, r, u, c: 12 floats)
     dr::Buf camacc;
+    // split backward: side-path queries, their radiances, per-(vertex, unit) query index, count
+    dr::Buf sq, sres, sqidx, scount;
+    bool split_backward = true;
     hipStream_t last_stream = nullptr;
     int device = 0;
     // measurement

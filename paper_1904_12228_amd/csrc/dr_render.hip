@@ -530,11 +530,14 @@ __device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int 
 // ---------------------------------------------------------------------------
 // backward over paths: secondary edges at every vertex + interior adjoint
 // ---------------------------------------------------------------------------
-template <int MAXD, int STK, bool CNT, bool MIX>
+// PH: 0 = all in one pass; 1 = rebuild the path, sample the secondary edges and
+// queue their side-path queries; 2 = rebuild the path, read the side
+// radiances of its queries and run the adjoint sweep.
+template <int MAXD, int STK, bool CNT, bool MIX, int PH = 0>
 __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, const RenderArgs& a, const TreeView& tv,
                                               const float* __restrict__ d_image, float* __restrict__ dV,
                                               float* __restrict__ dA, float* __restrict__ camacc, const MixArgs& mx,
-                                              int mbase, int* stk) {
+                                              int mbase, int* stk, const SplitArgs& sp = SplitArgs{}) {
     int lane = threadIdx.x;
     int* my = stk + lane;
     int m = mbase + lane;
@@ -543,11 +546,14 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
     bool have0 = false;          // vertex-1 triangle gradients, scattered per wave group
     int key0 = -1;
     float g0[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (PH == 1 && m < a.M)
+#pragma unroll
+        for (int kk = 0; kk < MAXD; ++kk) sp.qidx[(size_t)kk * a.M + m] = -1;
     if (m < a.M && (!a.mask || a.mask[m]) && a.depth >= 1 && a.ck_tri[m] >= 0) {
         int pix, px, py;
         uint32_t sid;
         unit_pixel(k, a, m, pix, px, py, sid);
-        float W0 = d_image[pix] / (float)a.spp;
+        float W0 = PH == 1 ? 0.0f : d_image[pix] / (float)a.spp;
         Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
         float4 j = rc.block(0);
         float sx = px + j.x, sy = py + j.y;
@@ -614,11 +620,17 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                 Rng rk{sid, a.view, kTagSedge + (uint32_t)(kk + 1), a.k0, a.k1};
                 float4 b0 = rk.block(0);
                 v3 p = xs[kk], n = ns[kk];
-                TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
                 float pdf;
                 bool dbg = m == a.debug_unit;
                 int ei;
-                if (MIX && mx.sec) {
+                int qi = -1;
+                if (PH == 2) {
+                    qi = sp.qidx[(size_t)kk * a.M + m];
+                    if (qi < 0) continue;
+                    ei = sp.q[qi].edge;
+                    pdf = sp.q[qi].pdf;
+                } else if (MIX && mx.sec) {
+                    TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
                     // proposal mixture: component from the third uniform of the
                     // block, proposal draw from the fourth
                     float pt;
@@ -632,26 +644,55 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     pdf = mx.mix * mx.q[ei] + (1.0f - mx.mix) * pt;
                     if (!(pdf > 0.0f) || s.ekind[ei] == 0) continue;
                 } else {
+                    TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
                     ei = tree_sample(tv, q, rk, b0.x, pdf, wk, dbg);
                 }
                 if (ei < 0) continue;
                 int4 e = s.edges[ei];
-                if (e.z == tri[kk] || e.w == tri[kk]) continue;
-                if (s.ekind[ei] == 2 && !silhouette_from(s, e, p)) continue;
+                if (PH != 2) {
+                    if (e.z == tri[kk] || e.w == tri[kk]) continue;
+                    if (s.ekind[ei] == 2 && !silhouette_from(s, e, p)) continue;
+                }
                 v3 pa = ld3(s.P, e.x), pb = ld3(s.P, e.y);
                 v3 w = pa + (pb - pa) * b0.y - p;
-                if (dot(n, w) <= kHorizon * s.diag) continue;
+                if (PH != 2 && dot(n, w) <= kHorizon * s.diag) continue;
                 v3 v0p = pa - p, v1p = pb - p;
                 v3 c = cross(v0p, v1p);
                 float cn = len(c);
-                if (cn == 0.0f) continue;
+                if (PH != 2 && cn == 0.0f) continue;
                 v3 nh = c * (1.0f / cn);
                 float wl = len(w);
                 v3 wh = w * (1.0f / wl);
                 v3 wp = nrm(wh + nh * kEps3), wm = nrm(wh - nh * kEps3);
                 int rem = a.depth - (kk + 1);
-                float Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, wk);
-                float Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, wk);
+                float Lp, Lm;
+                if (PH == 1) {
+                    // queue the side paths: one atomic per wave
+                    unsigned long long bal = __ballot(1);
+                    int leader = __ffsll(bal) - 1;
+                    int base = 0;
+                    if (lane == leader) base = atomicAdd(sp.count, __popcll(bal));
+                    base = __shfl(base, leader, BS);
+                    int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+                    SideQuery Q;
+                    Q.p[0] = p.x; Q.p[1] = p.y; Q.p[2] = p.z;
+                    Q.wp[0] = wp.x; Q.wp[1] = wp.y; Q.wp[2] = wp.z;
+                    Q.wm[0] = wm.x; Q.wm[1] = wm.y; Q.wm[2] = wm.z;
+                    Q.sid = sid;
+                    Q.edge = ei;
+                    Q.pdf = pdf;
+                    Q.k = kk;
+                    sp.q[slot] = Q;
+                    sp.qidx[(size_t)kk * a.M + m] = slot;
+                    continue;
+                } else if (PH == 2) {
+                    float2 L = sp.res[qi];
+                    Lp = L.x;
+                    Lm = L.y;
+                } else {
+                    Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, wk);
+                    Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, wk);
+                }
                 // the cosine is continuous across the edge; only the radiance jumps
                 float cosw = dot(n, wh);
                 float Fp = rho[kk] / kPi * cosw * Lp;
@@ -674,6 +715,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
             }
         }
         // ---- reverse sweep: interior term and propagation of vertex adjoints
+        if (PH == 1) nv = 0;
         bool interior = (a.terms & DR_TERM_INTERIOR) != 0;
         float Aft = 0.0f;          // radiance from later vertices per unit throughput there
         v3 carry = {0, 0, 0};      // adjoint of this vertex's position from the next ray-plane
@@ -751,6 +793,52 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
     int sh = blockIdx.x & (a.gshards - 1);
     backward_body<MAXD, STK, CNT, MIX>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride, camacc + 12 * sh,
                                        mx, blockIdx.x * BS, stk);
+}
+
+// Split backward, pass 1: secondary edge samples of every path vertex, their
+// side-path queries appended to a compact queue.
+template <int MAXD, int STK>
+__global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp) {
+    __shared__ int stk[STK * BS];
+    MixArgs mx{};
+    backward_body<MAXD, STK, false, false, 1>(s, k, a, tv, nullptr, nullptr, nullptr, nullptr, mx, blockIdx.x * BS, stk, sp);
+}
+
+// Split backward, pass 2: both one-sided radiances of every queued query, one
+// query per lane (no idle lanes), with the query's own Philox stream.
+template <int STK>
+__global__ __launch_bounds__(BS) void k_side(SceneView s, RenderArgs a, SplitArgs sp) {
+    __shared__ int stk[STK * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    NoWork wk;
+    int n = *sp.count;
+    for (int base = blockIdx.x * BS; base < n; base += gridDim.x * BS) {
+        int i = base + lane;
+        if (i < n) {
+            SideQuery Q = sp.q[i];
+            Rng rk{Q.sid, a.view, kTagSedge + (uint32_t)(Q.k + 1), a.k0, a.k1};
+            int rem = a.depth - (Q.k + 1);
+            v3 p = {Q.p[0], Q.p[1], Q.p[2]};
+            v3 wp = {Q.wp[0], Q.wp[1], Q.wp[2]}, wm = {Q.wm[0], Q.wm[1], Q.wm[2]};
+            float Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, wk);
+            float Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, wk);
+            sp.res[i] = make_float2(Lp, Lm);
+        }
+    }
+}
+
+// Split backward, pass 3: boundary contributions from the queued radiances and
+// the adjoint sweep.
+template <int MAXD, int STK>
+__global__ __launch_bounds__(BS) void k_bwd_adjoint(SceneView s, Cam k, RenderArgs a, TreeView tv,
+                                                    const float* __restrict__ d_image, float* __restrict__ dV,
+                                                    float* __restrict__ dA, float* __restrict__ camacc, SplitArgs sp) {
+    __shared__ int stk[STK * BS];
+    int sh = blockIdx.x & (a.gshards - 1);
+    MixArgs mx{};
+    backward_body<MAXD, STK, false, false, 2>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride,
+                                              camacc + 12 * sh, mx, blockIdx.x * BS, stk, sp);
 }
 
 __device__ inline void cam_finalize(const Cam& k, const float* __restrict__ acc, float* __restrict__ d_camera) {
@@ -912,6 +1000,10 @@ __global__ void k_fill_i32(int* __restrict__ p, int v) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
 }
 
+__global__ void k_fill_count(int* __restrict__ c) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *c = 0;
+}
+
 __global__ void k_fill(float* __restrict__ p, long n, float v) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -1060,9 +1152,32 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         EvScope ev(s, 2, st);
         a.counters = cbase ? cbase + 16 : nullptr;
         dim3 g(nblk(a.M, BS)), b(BS);
+        bool split = !use_mix && !a.counters && s->split_backward;
+        SplitArgs sp{};
+        // queue capacity: MAXD (the kernels' template depth: 1, 3 or 6) slots per unit
+        int maxd = o.max_depth <= 1 ? 1 : (o.max_depth <= 3 ? 3 : 6);
+        if (split) {
+            size_t cap = (size_t)maxd * (size_t)a.M;
+            if (s->sq.ensure(sizeof(SideQuery) * cap) != hipSuccess || s->sres.ensure(sizeof(float2) * cap) != hipSuccess ||
+                s->sqidx.ensure(sizeof(int) * cap) != hipSuccess || s->scount.ensure(sizeof(int)) != hipSuccess)
+                return DR_ERROR_OUT_OF_MEMORY;
+            sp.q = s->sq.as<SideQuery>();
+            sp.res = s->sres.as<float2>();
+            sp.qidx = s->sqidx.as<int>();
+            sp.count = s->scount.as<int>();
+            k_fill_count<<<1, 1, 0, st>>>(sp.count);
+        }
+        int side_grid = std::max(1, std::min(nblk((long)maxd * a.M, BS), 256 * 16));
+#define DR_SPLIT(D, S)                                                                                     \
+    k_bwd_sample<D, S><<<g, b, 0, st>>>(sv, cam, a, tv, sp);                                               \
+    k_side<S><<<side_grid, b, 0, st>>>(sv, a, sp);                                                         \
+    k_bwd_adjoint<D, S><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, sp);
 #define DR_BWD(D, S, C, X) k_backward<D, S, C, X><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx)
 #define DR_BWD_D(D)                                   \
-    if (use_mix) {                                    \
+    if (split) {                                      \
+        if (sm) { DR_SPLIT(D, 32) }                   \
+        else { DR_SPLIT(D, kStackDepth) }             \
+    } else if (use_mix) {                             \
         if (sm) DR_BWD(D, 32, false, true);           \
         else DR_BWD(D, kStackDepth, false, true);     \
     } else if (a.counters) {                          \
@@ -1081,6 +1196,7 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         }
 #undef DR_BWD_D
 #undef DR_BWD
+#undef DR_SPLIT
     }
     if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, shards, stride, 3L * s->V, d_vertices);
     if (d_albedo) k_reduce_shards<<<nblk(s->T, 256), 256, 0, st>>>(dA, shards, stride, s->T, d_albedo);
