@@ -49,7 +49,7 @@ static void release_all(drScene_t* s) {
                    &s->ecode_s, &s->elist_s, &s->ekeys, &s->eparent, &s->ecounter, &s->etree, &s->ebounds, &s->edepth,
                    &s->ck_tri, &s->ck_x, &s->ck_vis, &s->camacc};
     for (Buf* b : bufs) b->release();
-    for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount}) b->release();
+    for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount, &s->svtri, &s->svx}) b->release();
     s->counters.release();
     for (auto& e : s->evs) {
         (void)hipEventDestroy(e.a);

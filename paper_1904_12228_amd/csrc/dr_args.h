@@ -50,7 +50,9 @@ struct SplitArgs {
     SideQuery* q;                // [cap]
     float2* res;                 // [cap] (radiance on the + side, on the - side)
     int* qidx;                   // [MAXD][M] query of (vertex, unit), -1 if none
-    int* count;                  // queries appended
+    int* count;                  // [MAXD] queries appended per path vertex (segment kk starts at kk * M)
+    int* vtri;                   // [MAXD - 2][M] triangle hit by traced path vertex kk + 1 >= 2 (-1: miss)
+    float* vx;                   // [MAXD - 2][M][3] its position
 };
 
 // Everything one view of a batch needs on the device (fixed when the batch

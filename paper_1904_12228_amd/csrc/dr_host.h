@@ -78,7 +78,7 @@ struct drScene_t {
     // camera adjoint accumulator (f, r, u, c: 12 floats)
     dr::Buf camacc;
     // split backward: side-path queries, their radiances, per-(vertex, unit) query index, count
-    dr::Buf sq, sres, sqidx, scount;
+    dr::Buf sq, sres, sqidx, scount, svtri, svx;
     bool split_backward = true;
     hipStream_t last_stream = nullptr;
     int device = 0;

@@ -402,17 +402,17 @@ __device__ inline bool vsphere_prune(const ETChild& c, v3 pc) {
     return (out[0] && out[1]) || (in[0] && in[1]);
 }
 
-__device__ inline float cos_bound(const float lo[3], const float hi[3], v3 p, v3 n, float hz) {
-    v3 t1, t2;
-    onb(n, t1, t2);
-    float xl = 3e38f, xh = -3e38f, yl = 3e38f, yh = -3e38f, zh = -3e38f;
-    for (int c = 0; c < 8; ++c) {
-        v3 q = {((c & 1) ? hi[0] : lo[0]) - p.x, ((c & 2) ? hi[1] : lo[1]) - p.y, ((c & 4) ? hi[2] : lo[2]) - p.z};
-        float x = dot(t1, q), y = dot(t2, q), z = dot(n, q);
-        xl = fminf(xl, x); xh = fmaxf(xh, x);
-        yl = fminf(yl, y); yh = fmaxf(yh, y);
-        zh = fmaxf(zh, z);
-    }
+// Walter et al.'s bound on the cosine between the normal n and the direction
+// from p to any point of the box [lo, hi], in the frame (t1, t2, n): the box's
+// extent along each frame axis is its centre's projection plus or minus the
+// half-extents projected by the axis' absolute components.
+__device__ inline float cos_bound(const float lo[3], const float hi[3], v3 p, v3 n, v3 t1, v3 t2, float hz) {
+    v3 c = {(lo[0] + hi[0]) * 0.5f - p.x, (lo[1] + hi[1]) * 0.5f - p.y, (lo[2] + hi[2]) * 0.5f - p.z};
+    v3 h = {(hi[0] - lo[0]) * 0.5f, (hi[1] - lo[1]) * 0.5f, (hi[2] - lo[2]) * 0.5f};
+    float cx = dot(t1, c), ex = fabsf(t1.x) * h.x + fabsf(t1.y) * h.y + fabsf(t1.z) * h.z;
+    float cy = dot(t2, c), ey = fabsf(t2.x) * h.x + fabsf(t2.y) * h.y + fabsf(t2.z) * h.z;
+    float zh = dot(n, c) + fabsf(n.x) * h.x + fabsf(n.y) * h.y + fabsf(n.z) * h.z;
+    float xl = cx - ex, xh = cx + ex, yl = cy - ey, yh = cy + ey;
     float dx = (xl <= 0.0f && xh >= 0.0f) ? 0.0f : fminf(fabsf(xl), fabsf(xh));
     float dy = (yl <= 0.0f && yh >= 0.0f) ? 0.0f : fminf(fabsf(yl), fabsf(yh));
     float dxy2 = dx * dx + dy * dy;
@@ -426,7 +426,14 @@ struct TreeCtx {
     v3 p, n, cam;
     int tri;
     float hz, pad;
+    v3 t1, t2;     // tangent frame of n (Duff et al.)
 };
+
+__device__ inline TreeCtx tree_ctx(const SceneView* s, v3 p, v3 n, v3 cam, int tri, float hz, float pad) {
+    TreeCtx q{s, p, n, cam, tri, hz, pad, {0, 0, 0}, {0, 0, 0}};
+    onb(n, q.t1, q.t2);
+    return q;
+}
 
 __device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, int h2, const float* plo, const float* phi) {
     if (ref == 0) return 0.0f;
@@ -435,7 +442,7 @@ __device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, 
         if (e.z == q.tri || e.w == q.tri) return 0.0f;
     }
     if (h2 && vsphere_prune(c, q.p - q.cam)) return 0.0f;
-    float b = cos_bound(c.lo, c.hi, q.p, q.n, q.hz);
+    float b = cos_bound(c.lo, c.hi, q.p, q.n, q.t1, q.t2, q.hz);
     if (b <= 0.0f) return 0.0f;
     const float pv[3] = {q.p.x, q.p.y, q.p.z};
     bool in = true;
@@ -596,8 +603,22 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     if (t2 < 0) break;
                     const float* cx = a.ck_x + 3 * ((size_t)a.M + m);
                     x2 = {cx[0], cx[1], cx[2]};
+                } else if (PH == 2) {
+                    // the sampling pass traced this vertex: take its hit
+                    size_t slot = (size_t)(kk - 1) * a.M + m;
+                    t2 = sp.vtri[slot];
+                    if (t2 < 0) break;
+                    x2 = {sp.vx[3 * slot], sp.vx[3 * slot + 1], sp.vx[3 * slot + 2]};
                 } else {
                     Hit h = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, wk);
+                    if (PH == 1) {
+                        size_t slot = (size_t)(kk - 1) * a.M + m;
+                        sp.vtri[slot] = h.tri;
+                        if (h.tri >= 0) {
+                            v3 xh = hit_point(tri_geom(s, h.tri), x, w);
+                            sp.vx[3 * slot] = xh.x; sp.vx[3 * slot + 1] = xh.y; sp.vx[3 * slot + 2] = xh.z;
+                        }
+                    }
                     if (h.tri < 0) break;
                     t2 = h.tri;
                     x2 = hit_point(tri_geom(s, t2), x, w);
@@ -630,7 +651,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     ei = sp.q[qi].edge;
                     pdf = sp.q[qi].pdf;
                 } else if (MIX && mx.sec) {
-                    TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
+                    TreeCtx q = tree_ctx(&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag);
                     // proposal mixture: component from the third uniform of the
                     // block, proposal draw from the fourth
                     float pt;
@@ -644,7 +665,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     pdf = mx.mix * mx.q[ei] + (1.0f - mx.mix) * pt;
                     if (!(pdf > 0.0f) || s.ekind[ei] == 0) continue;
                 } else {
-                    TreeCtx q{&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag};
+                    TreeCtx q = tree_ctx(&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag);
                     ei = tree_sample(tv, q, rk, b0.x, pdf, wk, dbg);
                 }
                 if (ei < 0) continue;
@@ -671,9 +692,11 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     unsigned long long bal = __ballot(1);
                     int leader = __ffsll(bal) - 1;
                     int base = 0;
-                    if (lane == leader) base = atomicAdd(sp.count, __popcll(bal));
+                    // one queue segment of a.M slots per path vertex, so that
+                    // the side paths of a segment all have the same length
+                    if (lane == leader) base = atomicAdd(&sp.count[kk], __popcll(bal));
                     base = __shfl(base, leader, BS);
-                    int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+                    int slot = kk * a.M + base + __popcll(bal & ((1ull << lane) - 1ull));
                     SideQuery Q;
                     Q.p[0] = p.x; Q.p[1] = p.y; Q.p[2] = p.z;
                     Q.wp[0] = wp.x; Q.wp[1] = wp.y; Q.wp[2] = wp.z;
@@ -807,15 +830,15 @@ __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArg
 // Split backward, pass 2: both one-sided radiances of every queued query, one
 // query per lane (no idle lanes), with the query's own Philox stream.
 template <int STK>
-__global__ __launch_bounds__(BS) void k_side(SceneView s, RenderArgs a, SplitArgs sp) {
+__global__ __launch_bounds__(BS) void k_side(SceneView s, RenderArgs a, SplitArgs sp, int kk) {
     __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
     NoWork wk;
-    int n = *sp.count;
+    int n = sp.count[kk];
     for (int base = blockIdx.x * BS; base < n; base += gridDim.x * BS) {
-        int i = base + lane;
-        if (i < n) {
+        int i = kk * a.M + base + lane;
+        if (base + lane < n) {
             SideQuery Q = sp.q[i];
             Rng rk{Q.sid, a.view, kTagSedge + (uint32_t)(Q.k + 1), a.k0, a.k1};
             int rem = a.depth - (Q.k + 1);
@@ -1000,8 +1023,8 @@ __global__ void k_fill_i32(int* __restrict__ p, int v) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
 }
 
-__global__ void k_fill_count(int* __restrict__ c) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *c = 0;
+__global__ void k_fill_count(int* __restrict__ c, int n) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
 __global__ void k_fill(float* __restrict__ p, long n, float v) {
@@ -1158,19 +1181,24 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         int maxd = o.max_depth <= 1 ? 1 : (o.max_depth <= 3 ? 3 : 6);
         if (split) {
             size_t cap = (size_t)maxd * (size_t)a.M;
+            // traced vertices 2 .. MAXD-1 (path vertex index kk + 1 >= 2, slot kk - 1)
+            size_t vcap = (size_t)std::max(maxd - 2, 1) * (size_t)a.M;
             if (s->sq.ensure(sizeof(SideQuery) * cap) != hipSuccess || s->sres.ensure(sizeof(float2) * cap) != hipSuccess ||
-                s->sqidx.ensure(sizeof(int) * cap) != hipSuccess || s->scount.ensure(sizeof(int)) != hipSuccess)
+                s->sqidx.ensure(sizeof(int) * cap) != hipSuccess || s->scount.ensure(sizeof(int) * 6) != hipSuccess ||
+                s->svtri.ensure(sizeof(int) * vcap) != hipSuccess || s->svx.ensure(sizeof(float) * 3 * vcap) != hipSuccess)
                 return DR_ERROR_OUT_OF_MEMORY;
+            sp.vtri = s->svtri.as<int>();
+            sp.vx = s->svx.as<float>();
             sp.q = s->sq.as<SideQuery>();
             sp.res = s->sres.as<float2>();
             sp.qidx = s->sqidx.as<int>();
             sp.count = s->scount.as<int>();
-            k_fill_count<<<1, 1, 0, st>>>(sp.count);
+            k_fill_count<<<1, 64, 0, st>>>(sp.count, maxd);
         }
-        int side_grid = std::max(1, std::min(nblk((long)maxd * a.M, BS), 256 * 16));
+        int side_grid = std::max(1, std::min(nblk((long)a.M, BS), 256 * 16));
 #define DR_SPLIT(D, S)                                                                                     \
     k_bwd_sample<D, S><<<g, b, 0, st>>>(sv, cam, a, tv, sp);                                               \
-    k_side<S><<<side_grid, b, 0, st>>>(sv, a, sp);                                                         \
+    for (int kq = 0; kq < std::min(o.max_depth, D); ++kq) k_side<S><<<side_grid, b, 0, st>>>(sv, a, sp, kq);     \
     k_bwd_adjoint<D, S><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, sp);
 #define DR_BWD(D, S, C, X) k_backward<D, S, C, X><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx)
 #define DR_BWD_D(D)                                   \
