@@ -1319,8 +1319,10 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 cp.dx = cm.dx = pv.dx;
                 cp.dw = cm.dw = 8 + pv.dx / wl;
                 cp.kmax = cm.kmax = pv.kappa;
-                double Lp = radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wp, s.tmin, false, rem, nullptr, &cp);
-                double Lm = radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wm, s.tmin, false, rem, nullptr, &cm);
+                // the same limit rule as for primary edges
+                bool same = closest(s, p, wp, s.tmin, 1e300, U).tri == closest(s, p, wm, s.tmin, 1e300, U).tri;
+                double Lp = same ? 0.0 : radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wp, s.tmin, false, rem, nullptr, &cp);
+                double Lm = same ? 0.0 : radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wm, s.tmin, false, rem, nullptr, &cm);
                 double kap_s = std::max(pv.kappa, std::max(cp.kmax, cm.kmax)) + pv.dx / wl;
                 // The cosine factor is continuous across the edge: both one-sided
                 // limits share the cosine at the edge point; only L jumps.
@@ -1367,10 +1369,13 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             V3d cpos = vw.cam.c;
             Cond cu, cl;
             cu.dx = cl.dx = 4 * length(cpos);
-            double fu = radiance_impl<double>(Ev, U, rp, 0, cpos, cam_dir(vw.cam, x + kEpsPx * nx, y + kEpsPx * ny),
-                                              C.oc->near_clip, true, o.max_depth, nullptr, &cu);
-            double fl = radiance_impl<double>(Ev, U, rp, 0, cpos, cam_dir(vw.cam, x - kEpsPx * nx, y - kEpsPx * ny),
-                                              C.oc->near_clip, true, o.max_depth, nullptr, &cl);
+            V3d du = cam_dir(vw.cam, x + kEpsPx * nx, y + kEpsPx * ny), dl = cam_dir(vw.cam, x - kEpsPx * nx, y - kEpsPx * ny);
+            // Both one-sided rays on the same triangle (or both escaping): the
+            // edge is no visible discontinuity at this point, the one-sided
+            // limits coincide and the sample contributes nothing.
+            bool same = closest(s, cpos, du, C.oc->near_clip, 1e300, U).tri == closest(s, cpos, dl, C.oc->near_clip, 1e300, U).tri;
+            double fu = same ? 0.0 : radiance_impl<double>(Ev, U, rp, 0, cpos, du, C.oc->near_clip, true, o.max_depth, nullptr, &cu);
+            double fl = same ? 0.0 : radiance_impl<double>(Ev, U, rp, 0, cpos, dl, C.oc->near_clip, true, o.max_depth, nullptr, &cl);
             double kap_p = std::max(cu.kmax, cl.kmax);
             {
                 // a near-clipped endpoint sits at depth `near`: its projection and

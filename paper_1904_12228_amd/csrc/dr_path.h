@@ -103,13 +103,12 @@ __device__ inline v3 cosine_dir(v3 n, float u0, float u1) {
     return t1 * (r * cp) + t2 * (r * sp) + n * sqrtf(1.0f - u0);
 }
 
-// Radiance arriving along a ray: emission at the first hit, then NEE at path
-// vertices 1..budget with cosine continuation between them. camera: misses
-// return the background and t_min is the near clip.
+// Radiance arriving along the ray o + t d whose first hit is h: emission at
+// the hit, then NEE at path vertices 1..budget with cosine continuation
+// between them. camera: a miss returns the background.
 template <class W>
-__device__ inline float radiance(const SceneView& s, const Rng& rng, int base, v3 o, v3 d, float tmin, bool camera,
-                                 int budget, int* stk, int stride, W& wk) {
-    Hit h = trace_closest(s, o, d, tmin, 3.0e38f, stk, stride, wk);
+__device__ inline float radiance_hit(const SceneView& s, const Rng& rng, int base, v3 o, v3 d, const Hit& h, bool camera,
+                                     int budget, int* stk, int stride, W& wk) {
     if (h.tri < 0) return camera ? s.background : 0.0f;
     int tri = h.tri;
     TriGeom g = tri_geom(s, tri);
@@ -140,7 +139,30 @@ __device__ inline float radiance(const SceneView& s, const Rng& rng, int base, v
     return L;
 }
 
-// Projection to pixels (y down).
+// Radiance arriving at o from direction d (ray from o, first hit in (tmin, inf)).
+template <class W>
+__device__ inline float radiance(const SceneView& s, const Rng& rng, int base, v3 o, v3 d, float tmin, bool camera,
+                                 int budget, int* stk, int stride, W& wk) {
+    Hit h = trace_closest(s, o, d, tmin, 3.0e38f, stk, stride, wk);
+    return radiance_hit(s, rng, base, o, d, h, camera, budget, stk, stride, wk);
+}
+
+// The two one-sided radiances of a boundary sample, along d+ and d- just off
+// the edge. When both rays first hit the same triangle (or both escape), the
+// edge is not a visible discontinuity there: the one-sided limits coincide and
+// both values are returned as 0 without tracing the paths further.
+template <class W>
+__device__ inline void radiance_pair(const SceneView& s, const Rng& rng, int base, v3 o, v3 dp, v3 dm, float tmin,
+                                     bool camera, int budget, int* stk, int stride, W& wk, float& Lp, float& Lm) {
+    Hit hp = trace_closest(s, o, dp, tmin, 3.0e38f, stk, stride, wk);
+    Hit hm = trace_closest(s, o, dm, tmin, 3.0e38f, stk, stride, wk);
+    if (hp.tri == hm.tri) {
+        Lp = Lm = 0.0f;
+        return;
+    }
+    Lp = radiance_hit(s, rng, base, o, dp, hp, camera, budget, stk, stride, wk);
+    Lm = radiance_hit(s, rng, base, o, dm, hm, camera, budget, stk, stride, wk);
+}
 __device__ inline void project(const Cam& k, v3 P, float& sx, float& sy) {
     v3 q = P - k.c;
     float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);

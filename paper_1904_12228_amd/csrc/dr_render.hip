@@ -328,8 +328,9 @@ __device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, c
         float dx = Ax - Bx, dy = Ay - By;
         float nl = sqrtf(dx * dx + dy * dy);
         float nx = (Ay - By) / nl, ny = (Bx - Ax) / nl;
-        float fu = radiance(s, rp, 0, k.c, cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), k.nearc, true, a.depth, my, BS, wk);
-        float fl = radiance(s, rp, 0, k.c, cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny), k.nearc, true, a.depth, my, BS, wk);
+        float fu, fl;
+        radiance_pair(s, rp, 0, k.c, cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny),
+                      k.nearc, true, a.depth, my, BS, wk, fu, fl);
         if (m == a.debug_unit)
             printf("punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g n %.9g %.9g fu %.9g fl %.9g total %.9g\n", m, ei, x,
                    y, Ax, Ay, Bx, By, nx, ny, fu, fl, total);
@@ -713,8 +714,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     Lp = L.x;
                     Lm = L.y;
                 } else {
-                    Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, wk);
-                    Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, wk);
+                    radiance_pair(s, rk, kSideBlockBase, p, wp, wm, s.tmin, false, rem, my, BS, wk, Lp, Lm);
                 }
                 // the cosine is continuous across the edge; only the radiance jumps
                 float cosw = dot(n, wh);
@@ -844,8 +844,8 @@ __global__ __launch_bounds__(BS) void k_side(SceneView s, RenderArgs a, SplitArg
             int rem = a.depth - (Q.k + 1);
             v3 p = {Q.p[0], Q.p[1], Q.p[2]};
             v3 wp = {Q.wp[0], Q.wp[1], Q.wp[2]}, wm = {Q.wm[0], Q.wm[1], Q.wm[2]};
-            float Lp = radiance(s, rk, kSideBlockBase, p, wp, s.tmin, false, rem, my, BS, wk);
-            float Lm = radiance(s, rk, kSideBlockBase, p, wm, s.tmin, false, rem, my, BS, wk);
+            float Lp, Lm;
+            radiance_pair(s, rk, kSideBlockBase, p, wp, wm, s.tmin, false, rem, my, BS, wk, Lp, Lm);
             sp.res[i] = make_float2(Lp, Lm);
         }
     }
