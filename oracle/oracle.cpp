@@ -1164,6 +1164,35 @@ S radiance_impl(const Env<S>& E, Unit& U, const Stream& rs, int base, const V3<S
     return L;
 }
 
+// Geometry buffers (Results, G-buffer / AOV outputs): one channel of the
+// first camera hit: 1-3 world position, 4-6 shading normal facing the ray,
+// 7 albedo; 0 on a miss. `cond` gets the first-vertex rounding model of
+// radiance_impl.
+template <class S>
+S aov_impl(const Env<S>& E, Unit& U, int aov, const V3<S>& o, const V3<S>& d0, double tmin, Cond* cond) {
+    const Scn& s = *E.s;
+    V3d dv = valv(d0);
+    Hit h = closest(s, valv(o), dv, tmin, 1e300, U);
+    if (h.tri < 0) return cst<S>(0.0);
+    int tri = h.tri;
+    V3<S> p0 = E.P(s.I[3 * tri]), p1 = E.P(s.I[3 * tri + 1]), p2 = E.P(s.I[3 * tri + 2]);
+    V3<S> x = ray_plane(o, d0, p0, p1, p2);
+    if (cond) {
+        double c = std::max(std::fabs(dot(normalize(dv), normalize(s.face_n(tri)))), 1e-6);
+        cond->dx = (cond->dx + h.t * length(dv) * cond->dw) / c + 4 * length(valv(x));
+        double e = min_edge(s, tri);
+        double dn = 4 + cond->dx * normal_spread(s, tri) / e;
+        cond->kmax = cond->kmax + 4 + cond->dx / e + dn + cond->dw / c;
+    }
+    if (aov <= 3) return aov == 1 ? x.x : (aov == 2 ? x.y : x.z);
+    if (aov <= 6) {
+        V3<S> ns = shading_normal(s, tri, x, p0, p1, p2);
+        if (!(dot(dv, s.face_n(tri)) < 0)) ns = -ns;
+        return aov == 4 ? ns.x : (aov == 5 ? ns.y : ns.z);
+    }
+    return E.albedo(tri);
+}
+
 // ---------------------------------------------------------------------------
 // Per-unit evaluation
 // ---------------------------------------------------------------------------
@@ -1244,7 +1273,8 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
     V3<D> dir = cam_dir(cam, sx, sy);
     Cond cmain;
     cmain.dx = 4 * length(valv(cam.c));
-    D Lr = radiance_impl<D>(Ed, U, rc, 0, cam.c, dir, C.oc->near_clip, true, o.max_depth, &verts, &cmain);
+    D Lr = o.aov ? aov_impl<D>(Ed, U, o.aov, cam.c, dir, C.oc->near_clip, &cmain)
+                 : radiance_impl<D>(Ed, U, rc, 0, cam.c, dir, C.oc->near_clip, true, o.max_depth, &verts, &cmain);
     std::vector<std::pair<int, double>> contrib;
     std::vector<double> sweep_mass_keys;
     std::vector<std::vector<std::pair<int, double>>> parts;
@@ -1262,7 +1292,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             sweep(C, L, Lr.i, wimg, parts.back());
         }
         // Secondary boundary term at every path vertex (one edge sample each).
-        if (o.secondary_edges && C.et) {
+        if (o.secondary_edges && C.et && !o.aov) {
             for (size_t kv = 0; kv < verts.size(); ++kv) {
                 int k = (int)kv + 1;
                 const PathVtx<D>& pv = verts[kv];
@@ -1374,8 +1404,10 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
             // edge is no visible discontinuity at this point, the one-sided
             // limits coincide and the sample contributes nothing.
             bool same = closest(s, cpos, du, C.oc->near_clip, 1e300, U).tri == closest(s, cpos, dl, C.oc->near_clip, 1e300, U).tri;
-            double fu = same ? 0.0 : radiance_impl<double>(Ev, U, rp, 0, cpos, du, C.oc->near_clip, true, o.max_depth, nullptr, &cu);
-            double fl = same ? 0.0 : radiance_impl<double>(Ev, U, rp, 0, cpos, dl, C.oc->near_clip, true, o.max_depth, nullptr, &cl);
+            double fu = same ? 0.0 : o.aov ? aov_impl<double>(Ev, U, o.aov, cpos, du, C.oc->near_clip, &cu)
+                                     : radiance_impl<double>(Ev, U, rp, 0, cpos, du, C.oc->near_clip, true, o.max_depth, nullptr, &cu);
+            double fl = same ? 0.0 : o.aov ? aov_impl<double>(Ev, U, o.aov, cpos, dl, C.oc->near_clip, &cl)
+                                     : radiance_impl<double>(Ev, U, rp, 0, cpos, dl, C.oc->near_clip, true, o.max_depth, nullptr, &cl);
             double kap_p = std::max(cu.kmax, cl.kmax);
             {
                 // a near-clipped endpoint sits at depth `near`: its projection and
@@ -1570,6 +1602,7 @@ void orc_secondary_forms(const double p_[3], const double v0_[3], const double v
 
 int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, orc_outputs* out) {
     if (!oc || !o || !out) return ORC_EINVAL;
+    if (o->aov < 0 || o->aov > 7) return ORC_EINVAL;
     if (o->spp <= 0 || o->max_depth < 0 || o->max_depth > 8) return ORC_EINVAL;
     if (oc->width <= 0 || oc->height <= 0 || oc->win_x0 < 0 || oc->win_y0 < 0 || oc->win_x1 > oc->width ||
         oc->win_y1 > oc->height || oc->win_x0 >= oc->win_x1 || oc->win_y0 >= oc->win_y1)
@@ -1581,7 +1614,7 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
     View vw;
     build_view(s, *oc, vw);
     ETree et;
-    bool need_tree = o->secondary_edges && o->max_depth >= 1 && out->d_image;
+    bool need_tree = o->secondary_edges && o->max_depth >= 1 && out->d_image && !o->aov;
     if (need_tree) {
         rc = build_etree(s, vw.cam.c, et);
         if (rc) return rc;

@@ -71,6 +71,11 @@ typedef struct {
     const double* edge_pdf;
     double  mix;
     int32_t mix_terms;
+    /* Geometry buffer instead of radiance (0 = radiance): the value of one
+     * channel at the first camera hit, 0 on a miss: 1-3 world position x/y/z,
+     * 4-6 shading normal x/y/z (facing the ray), 7 albedo. Gradients: interior
+     * term of that value and the primary boundary term (no secondary term). */
+    int32_t aov;
 } orc_options;
 
 typedef struct {
