@@ -114,6 +114,49 @@ def proposal_leg(threads_note=None):
             "train_loss": [loss0, loss1], "per_term": res, "gain_total": res["total"]["gain"]}
 
 
+def gbuffer_leg(S, cam, spp, d_image, reps=3):
+    """Geometry buffers at the benchmark workload: position (3 channels),
+    normal (3) and albedo, each rendered and differentiated (first hit,
+    interior + primary edge term) with the same loss gradient image."""
+    import torch
+
+    H, W = d_image.shape
+    dev = d_image.device
+    bufs = torch.empty((7, H, W), dtype=torch.float32, device=dev)
+    dv = torch.empty((S.num_vertices, 3), dtype=torch.float32, device=dev)
+    da = torch.empty((S.num_triangles,), dtype=torch.float32, device=dev)
+    dc = torch.empty((9,), dtype=torch.float32, device=dev)
+
+    d7 = d_image.expand(7, H, W).contiguous()
+
+    def all_step(i):
+        S.render(cam, spp, 0, seed=i, out=bufs, aov=8)
+        S.render_backward(cam, spp, 0, d7, seed=i, outs=(dv, da, dc), aov=8)
+
+    def per_channel_step(i):
+        for ch in range(1, 8):
+            S.render(cam, spp, 0, seed=i, out=bufs[ch - 1], aov=ch)
+            S.render_backward(cam, spp, 0, d_image, seed=i, outs=(dv, da, dc), aov=ch)
+
+    res = {}
+    for name, fn in (("all_channels_one_pass", all_step), ("one_pass_per_channel", per_channel_step)):
+        fn(100)
+        S.set_profiling(events=True, counters=False)
+        S.profile(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(reps):
+            fn(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        prof = S.profile(reset=True)
+        assert torch.isfinite(bufs).all() and torch.isfinite(dv).all(), "non-finite G-buffer output"
+        res[name] = {"ms_per_gbuffer_step": ms, "pixel_samples_per_s": W * H * spp / (ms * 1e-3),
+                     "kernel_ms_per_step": {k: prof[f"{k}_ms"] / reps for k in ("forward", "primary", "backward")}}
+    return {"workload": f"{W}x{H}, {spp} spp, 7 channels (position xyz, normal xyz, albedo), forward + backward",
+            **res}
+
+
 def inverse_leg(steps=200):
     """Batched inverse rendering on the 1,000-triangle scene: 32 seeded views
     (128^2 to 512^2, 8 to 64 spp, depth 1) in one batch, target images of the
@@ -191,6 +234,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal variance x time leg")
     ap.add_argument("--no-inverse", action="store_true", help="skip the batched inverse-rendering leg")
+    ap.add_argument("--no-gbuffer", action="store_true", help="skip the geometry-buffer leg")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one plain device copy of 256 MiB (reference for HBM byte counters)")
@@ -293,6 +337,9 @@ def main():
                      "algorithmic_bytes_per_launch": bwd_bytes},
         "kernels": kernels,
     }
+    if not args.no_gbuffer:
+        print("running the geometry-buffer leg", file=sys.stderr, flush=True)
+        out["gbuffer"] = gbuffer_leg(S, cam, spp, d_image)
     if not args.no_proposal:
         print("running the learned-proposal leg", file=sys.stderr, flush=True)
         out["proposal"] = proposal_leg()

@@ -111,6 +111,19 @@ typedef struct {
      * two endpoints (6 numbers). Its expectation does not depend on the
      * sampler: the training target of the learned proposal. */
     float*   edge_stats;
+    /* Geometry buffer in place of radiance (Ch. 5, Results: the method
+     * differentiates G-buffers as well): 0 = radiance; 1, 2, 3 = world
+     * position x, y, z of the camera ray's first hit; 4, 5, 6 = shading
+     * normal x, y, z there, turned to face the camera ray; 7 = albedo of the
+     * hit triangle; 8 = all seven at once, in which case drRender's image
+     * and drRenderBackward's d_image are [7][Hw][Ww] (channel c at offset
+     * (c-1)*Hw*Ww) and the gradient is that of the sum of the channels'
+     * losses. A camera ray that hits nothing gives 0. The gradient is the
+     * chain rule at the first hit (interior term) plus primary edge sampling
+     * (boundary term); there is no secondary term and max_depth is not used.
+     * Not combined with edge_pdf, edge_mix > 0 or edge_stats
+     * (DR_ERROR_INVALID_VALUE); batches take 0 only. */
+    int32_t  aov;
 } drRenderOptions;
 
 /* Creates a scene: validates sizes and indices (host copy of the topology),
@@ -120,6 +133,12 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* desc, hipStream_t stream
 
 /* Replaces all vertex positions ([V][3] device) and rebuilds the BVH. */
 drStatus drSceneUpdateVertices(drScene scene, const float* vertices, hipStream_t stream);
+
+/* Replaces all triangle albedos ([T] device, in [0, 1]) for material
+ * fitting (Ch. 5, Results: inverse rendering of material parameters);
+ * refreshes the edge kinds, which depend on the albedos of an edge's two
+ * faces. The values are not checked. */
+drStatus drSceneUpdateAlbedo(drScene scene, const float* albedo, hipStream_t stream);
 
 /* Host query of the scene's sizes. */
 drStatus drSceneGetInfo(drScene scene, int32_t* num_vertices, int32_t* num_triangles, int32_t* num_edges);

@@ -18,8 +18,8 @@ DR_TERM_SECONDARY = 4
 DR_TERM_ALL = 7
 
 # every entry point declared in include/diffrt.h
-EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneGetInfo", "drRender", "drRenderBackward",
-           "drAdamStep", "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy",
+EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneUpdateAlbedo", "drSceneGetInfo", "drRender",
+           "drRenderBackward", "drAdamStep", "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy",
            "drGetErrorString", "drEdgeFeatures", "drMlpForward", "drMlpSoftmaxXent", "drMlpBackward",
            "drSceneRefit", "drBatchCreate", "drBatchRefit", "drBatchAdvanceSeed", "drBatchForward", "drBatchBackward",
            "drBatchSetLaunch", "drBatchDestroy", "drAdamStepCounted"]
@@ -45,7 +45,7 @@ class RenderOptions(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("view_id", C.c_uint32), ("terms", C.c_uint32), ("unit_mask", C.c_void_p),
                 ("edge_pdf", C.c_void_p), ("edge_mix", C.c_float), ("edge_mix_terms", C.c_uint32),
-                ("edge_stats", C.c_void_p)]
+                ("edge_stats", C.c_void_p), ("aov", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -76,6 +76,7 @@ def load():
     sig = {
         "drSceneCreate": [C.POINTER(vp), C.POINTER(SceneDesc), vp],
         "drSceneUpdateVertices": [vp, vp, vp],
+        "drSceneUpdateAlbedo": [vp, vp, vp],
         "drSceneGetInfo": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "drRender": [vp, C.POINTER(Camera), C.POINTER(RenderOptions), vp, vp],
         "drRenderBackward": [vp, C.POINTER(Camera), C.POINTER(RenderOptions), vp, vp, vp, vp, vp],

@@ -40,9 +40,14 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 def options_struct(spp, max_depth, seed=0, view_id=0, terms=0, unit_mask=None, edge_pdf=None, edge_mix=0.0,
-                   edge_mix_terms=0, edge_stats=None) -> _lib.RenderOptions:
+                   edge_mix_terms=0, edge_stats=None, aov=0) -> _lib.RenderOptions:
     return _lib.RenderOptions(int(spp), int(max_depth), int(seed), int(view_id), int(terms), _ptr(unit_mask),
-                              _ptr(edge_pdf), float(edge_mix), int(edge_mix_terms), _ptr(edge_stats))
+                              _ptr(edge_pdf), float(edge_mix), int(edge_mix_terms), _ptr(edge_stats), int(aov))
+
+
+# geometry-buffer channels of drRenderOptions.aov
+AOV = {"radiance": 0, "position_x": 1, "position_y": 2, "position_z": 3, "normal_x": 4, "normal_y": 5,
+       "normal_z": 6, "albedo": 7, "all": 8}
 
 
 class Scene:
@@ -74,22 +79,35 @@ class Scene:
         self.vertices = v
         _lib.check(_lib.load().drSceneUpdateVertices(self._h, _ptr(v), _stream()), "drSceneUpdateVertices")
 
-    def render(self, cam, spp, max_depth, seed=0, view_id=0, unit_mask=None, out=None):
+    def update_albedo(self, albedo):
+        a = _dev(albedo, torch.float32, self.device)
+        assert a.shape == (self.num_triangles,)
+        self.albedo = a
+        _lib.check(_lib.load().drSceneUpdateAlbedo(self._h, _ptr(a), _stream()), "drSceneUpdateAlbedo")
+
+    def render(self, cam, spp, max_depth, seed=0, view_id=0, unit_mask=None, out=None, aov=0):
+        """Window image [H, W]: radiance, or with aov in 1..7 one geometry-buffer
+        channel (AOV names them); aov = 8: all seven channels, [7, H, W]."""
         x0, y0, x1, y1 = cam.win()
-        img = out if out is not None else torch.empty((y1 - y0, x1 - x0), dtype=torch.float32, device=self.device)
+        shape = (7, y1 - y0, x1 - x0) if aov == 8 else (y1 - y0, x1 - x0)
+        img = out if out is not None else torch.empty(shape, dtype=torch.float32, device=self.device)
+        assert img.numel() == 7 ** (aov == 8) * (y1 - y0) * (x1 - x0) and img.is_contiguous() and img.dtype == torch.float32
         c = camera_struct(cam)
-        o = options_struct(spp, max_depth, seed, view_id, 0, unit_mask)
+        o = options_struct(spp, max_depth, seed, view_id, 0, unit_mask, aov=aov)
         _lib.check(_lib.load().drRender(self._h, C.byref(c), C.byref(o), _ptr(img), _stream()), "drRender")
         return img
 
     def render_backward(self, cam, spp, max_depth, d_image, seed=0, view_id=0, terms=0, unit_mask=None,
                         want=("vertices", "albedo", "camera"), outs=None, edge_pdf=None, edge_mix=0.0,
-                        edge_mix_terms=0, edge_stats=None):
+                        edge_mix_terms=0, edge_stats=None, aov=0):
         """Gradients w.r.t. vertices [V,3], albedo [T] and camera [9]. With
         edge_pdf ([E] device distribution) and edge_mix > 0 the edge samples
         are drawn from the proposal mixture; edge_stats ([E] float32 device
-        tensor) receives the harvest statistic."""
+        tensor) receives the harvest statistic. aov selects the image being
+        differentiated, as in render."""
         d_image = _dev(d_image, torch.float32, self.device)
+        x0, y0, x1, y1 = cam.win()
+        assert d_image.numel() == (7 if aov == 8 else 1) * (y1 - y0) * (x1 - x0), "d_image size"
         if outs is None:
             dv = torch.empty((self.num_vertices, 3), dtype=torch.float32, device=self.device) if "vertices" in want else None
             da = torch.empty((self.num_triangles,), dtype=torch.float32, device=self.device) if "albedo" in want else None
@@ -102,7 +120,7 @@ class Scene:
         if edge_stats is not None:
             assert edge_stats.dtype == torch.float32 and edge_stats.is_contiguous() and edge_stats.numel() == self.num_edges
         o = options_struct(spp, max_depth, seed, view_id, terms, unit_mask, edge_pdf, edge_mix, edge_mix_terms,
-                           edge_stats)
+                           edge_stats, aov)
         _lib.check(_lib.load().drRenderBackward(self._h, C.byref(c), C.byref(o), _ptr(d_image), _ptr(dv), _ptr(da),
                                                 _ptr(dc), _stream()), "drRenderBackward")
         return dv, da, dc

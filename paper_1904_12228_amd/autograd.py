@@ -42,6 +42,57 @@ def render(scene: api.Scene, vertices: torch.Tensor, camera9: torch.Tensor, cam:
     return _RenderFn.apply(vertices, camera9, scene, cam, spp, depth, seed, view_id)
 
 
+ALL_CHANNELS = (1, 2, 3, 4, 5, 6, 7)
+
+
+class _GBufferFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, vertices, camera9, albedo, scene: api.Scene, cam: Camera, spp: int, seed: int, channels, unit_mask):
+        scene.update_vertices(vertices)
+        if albedo is not None:
+            scene.update_albedo(albedo)
+        c = Camera.from_params9(camera9.detach().cpu().numpy(), cam)
+        x0, y0, x1, y1 = c.win()
+        out = torch.empty((len(channels), y1 - y0, x1 - x0), dtype=torch.float32, device=vertices.device)
+        if tuple(channels) == ALL_CHANNELS:
+            scene.render(c, spp, 0, seed=seed, unit_mask=unit_mask, out=out, aov=8)
+        else:
+            for i, ch in enumerate(channels):
+                scene.render(c, spp, 0, seed=seed, unit_mask=unit_mask, out=out[i], aov=ch)
+        ctx.args = (scene, c, spp, seed, tuple(channels), unit_mask)
+        ctx.cam_device = camera9.device
+        ctx.has_albedo = albedo is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, d_out):
+        scene, c, spp, seed, channels, unit_mask = ctx.args
+        if channels == ALL_CHANNELS:
+            dv, da, dc = scene.render_backward(c, spp, 0, d_out.contiguous(), seed=seed, unit_mask=unit_mask, aov=8)
+            return dv, dc.to(ctx.cam_device), da if ctx.has_albedo else None, None, None, None, None, None, None
+        dv = dc = da = None
+        for i, ch in enumerate(channels):
+            g = d_out[i].contiguous()
+            v, a, k = scene.render_backward(c, spp, 0, g, seed=seed, unit_mask=unit_mask, aov=ch)
+            dv = v if dv is None else dv + v
+            da = a if da is None else da + a
+            dc = k if dc is None else dc + k
+        return dv, dc.to(ctx.cam_device), da if ctx.has_albedo else None, None, None, None, None, None, None
+
+
+def gbuffer(scene: api.Scene, vertices: torch.Tensor, camera9: torch.Tensor, cam: Camera, spp: int, seed: int = 0,
+            channels=ALL_CHANNELS, albedo: torch.Tensor | None = None, unit_mask=None) -> torch.Tensor:
+    """Differentiable geometry buffers [len(channels), H, W] (channel numbers
+    as in api.AOV: 1-3 position, 4-6 normal facing the camera, 7 albedo), each
+    the box-filtered mean of its value at the first hit of `spp` camera rays
+    per pixel (0 where a ray escapes). Gradients reach vertices, camera and,
+    when given, albedo ([T]); a deferred-shading function of the buffers
+    written in torch differentiates through them (Ch. 5, Results: G-buffers
+    and deferred shading). The seven channels in order take one forward and
+    one backward call (aov = 8), other selections one call per channel."""
+    return _GBufferFn.apply(vertices, camera9, albedo, scene, cam, spp, seed, tuple(channels), unit_mask)
+
+
 class DeviceAdam:
     """Adam with bias correction, one drAdamStep launch per parameter tensor."""
 

@@ -72,7 +72,8 @@ bool valid_camera(const drCamera* c) {
 bool valid_options(const drRenderOptions* o) {
     return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0 &&
            o->edge_mix >= 0.0f && o->edge_mix < 1.0f &&
-           (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) == 0;
+           (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) == 0 && o->aov >= 0 && o->aov <= 8 &&
+           (o->aov == 0 || (o->edge_mix == 0.0f && !o->edge_stats));
 }
 
 ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {
@@ -92,6 +93,7 @@ ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o
     k.seed = o.seed;
     k.view = o.view_id;
     k.mask = o.unit_mask;
+    k.aov = o.aov;
     k.version = s->version;
     return k;
 }
@@ -217,6 +219,17 @@ drStatus drSceneUpdateVertices(drScene s, const float* vertices, hipStream_t st)
     return build_scene_static(s, st);
 }
 
+drStatus drSceneUpdateAlbedo(drScene s, const float* albedo, hipStream_t st) {
+    if (!s || !albedo) return DR_ERROR_INVALID_VALUE;
+    API_CHECK(hipMemcpyAsync(s->alb.p, albedo, sizeof(float) * s->T, hipMemcpyDeviceToDevice, st));
+    // edge kinds depend on the albedos of the two faces; paths stop at black surfaces
+    s->version++;
+    s->tree_valid = false;
+    s->ck_valid = false;
+    s->last_stream = st;
+    return build_scene_static(s, st);
+}
+
 drStatus drSceneGetInfo(drScene s, int32_t* nv, int32_t* nt, int32_t* ne) {
     if (!s) return DR_ERROR_INVALID_VALUE;
     if (nv) *nv = s->V;
@@ -270,9 +283,9 @@ drStatus drRenderBackward(drScene s, const drCamera* c, const drRenderOptions* o
         s->ck_valid = true;
     }
     uint32_t terms = o->terms ? o->terms : DR_TERM_ALL;
-    bool need_tree = o->max_depth >= 1 && (terms & DR_TERM_SECONDARY);
+    bool need_tree = o->max_depth >= 1 && (terms & DR_TERM_SECONDARY) && !o->aov;
     ViewKey tkey = key;
-    tkey.spp = 0; tkey.seed = 0; tkey.view = 0; tkey.mask = nullptr; tkey.depth = 0;
+    tkey.spp = 0; tkey.seed = 0; tkey.view = 0; tkey.mask = nullptr; tkey.depth = 0; tkey.aov = 0;
     r = build_view_edges(s, cam, tkey, need_tree, st);
     if (r != DR_SUCCESS) return r;
     r = launch_backward(s, cam, *o, d_image, d_vertices, d_albedo, d_camera, st);

@@ -23,6 +23,7 @@ struct RenderArgs {
     // (12 floats apart); the copies are summed after the kernels
     int gshards;
     long gstride;
+    int aov;           // 0: radiance; 1..7: geometry-buffer channel (the _aov kernels)
 };
 
 // Learned-proposal mixture and harvest (the <.., MIX = true> kernel variants).

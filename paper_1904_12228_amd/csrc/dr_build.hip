@@ -613,7 +613,7 @@ bool ViewKey::operator==(const ViewKey& o) const {
         if (cam[i] != o.cam[i]) return false;
     return fov == o.fov && nearc == o.nearc && w == o.w && h == o.h && win[0] == o.win[0] && win[1] == o.win[1] &&
            win[2] == o.win[2] && win[3] == o.win[3] && spp == o.spp && depth == o.depth && seed == o.seed &&
-           view == o.view && mask == o.mask && version == o.version;
+           view == o.view && mask == o.mask && aov == o.aov && version == o.version;
 }
 
 drStatus build_view_edges(drScene_t* s, const Cam& cam, const ViewKey& key, bool need_tree, hipStream_t st) {

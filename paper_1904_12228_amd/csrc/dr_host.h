@@ -41,6 +41,7 @@ struct ViewKey {
     uint64_t seed;
     uint32_t view;
     const uint8_t* mask;
+    int aov;
     uint64_t version;
     bool operator==(const ViewKey& o) const;
 };

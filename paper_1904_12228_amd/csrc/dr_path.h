@@ -163,6 +163,67 @@ __device__ inline void radiance_pair(const SceneView& s, const Rng& rng, int bas
     Lp = radiance_hit(s, rng, base, o, dp, hp, camera, budget, stk, stride, wk);
     Lm = radiance_hit(s, rng, base, o, dm, hm, camera, budget, stk, stride, wk);
 }
+
+// Geometry-buffer channel at the first hit x of triangle tri along d (Ch. 5,
+// Results: G-buffers): 1..3 position, 4..6 shading normal facing the ray,
+// 7 albedo; aov = 8 asks for all seven (aov_values).
+__device__ inline float aov_value(const SceneView& s, int aov, int tri, const TriGeom& g, v3 x, v3 d) {
+    if (aov <= 3) return aov == 1 ? x.x : (aov == 2 ? x.y : x.z);
+    if (aov <= 6) {
+        v3 n = shading_normal(s, tri, g, x);
+        if (!(dot(d, cross(g.e1, g.e2)) < 0.0f)) n = -n;
+        return aov == 4 ? n.x : (aov == 5 ? n.y : n.z);
+    }
+    return s.alb[tri];
+}
+
+// All seven channels at once (aov = 8): v[c - 1] = channel c.
+__device__ inline void aov_values(const SceneView& s, int tri, const TriGeom& g, v3 x, v3 d, float (&v)[7]) {
+    v3 n = shading_normal(s, tri, g, x);
+    if (!(dot(d, cross(g.e1, g.e2)) < 0.0f)) n = -n;
+    v[0] = x.x; v[1] = x.y; v[2] = x.z;
+    v[3] = n.x; v[4] = n.y; v[5] = n.z;
+    v[6] = s.alb[tri];
+}
+
+// Loss-weighted jump of the buffer across a primary boundary sample:
+// sum over the channels of dI[channel] * (value on the + side - value on the
+// - side), a ray that escapes giving 0. dI points at the sample's pixel in the
+// first channel's loss gradient; channels are npix floats apart. Zero when
+// the two rays hit the same triangle, as for radiance.
+template <class W>
+__device__ inline float aov_jump(const SceneView& s, int aov, v3 o, v3 dp, v3 dm, float tmin, const float* dI, int npix,
+                                 int* stk, int stride, W& wk) {
+    Hit hp = trace_closest(s, o, dp, tmin, 3.0e38f, stk, stride, wk);
+    Hit hm = trace_closest(s, o, dm, tmin, 3.0e38f, stk, stride, wk);
+    if (hp.tri == hm.tri) return 0.0f;
+    if (aov != 8) {
+        float Fp = 0.0f, Fm = 0.0f;
+        if (hp.tri >= 0) {
+            TriGeom g = tri_geom(s, hp.tri);
+            Fp = aov_value(s, aov, hp.tri, g, hit_point(g, o, dp), dp);
+        }
+        if (hm.tri >= 0) {
+            TriGeom g = tri_geom(s, hm.tri);
+            Fm = aov_value(s, aov, hm.tri, g, hit_point(g, o, dm), dm);
+        }
+        return dI[0] * (Fp - Fm);
+    }
+    float vp[7] = {0, 0, 0, 0, 0, 0, 0}, vm[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (hp.tri >= 0) {
+        TriGeom g = tri_geom(s, hp.tri);
+        aov_values(s, hp.tri, g, hit_point(g, o, dp), dp, vp);
+    }
+    if (hm.tri >= 0) {
+        TriGeom g = tri_geom(s, hm.tri);
+        aov_values(s, hm.tri, g, hit_point(g, o, dm), dm, vm);
+    }
+    float j = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) j += dI[(size_t)c * npix] * (vp[c] - vm[c]);
+    return j;
+}
+
 __device__ inline void project(const Cam& k, v3 P, float& sx, float& sy) {
     v3 q = P - k.c;
     float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);

@@ -131,6 +131,62 @@ __global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a
     forward_body<STK, CNT>(s, k, a, image, reduce, blockIdx.x * BS, stk);
 }
 
+// Geometry buffers (Ch. 5, Results): channel a.aov (1..7) of the first hit of
+// each camera ray, or all seven (a.aov = 8; image [7][Hw][Ww]); 0 where the
+// ray escapes. Stores the first-hit checkpoint the backward pass reuses.
+template <int STK>
+__global__ __launch_bounds__(BS) void k_forward_aov(SceneView s, Cam k, RenderArgs a, float* __restrict__ image,
+                                                    int reduce) {
+    __shared__ int stk[STK * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    int m = blockIdx.x * BS + lane;
+    NoWork wk;
+    float v[7] = {0, 0, 0, 0, 0, 0, 0};
+    int pix = 0;
+    if (m < a.M) {
+        int px, py;
+        uint32_t sid;
+        unit_pixel(k, a, m, pix, px, py, sid);
+        int ckt = -1;
+        v3 ckx = {0, 0, 0};
+        if (!a.mask || a.mask[m]) {
+            Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
+            float4 j = rc.block(0);
+            v3 d = cam_dir(k, px + j.x, py + j.y);
+            Hit h = trace_closest(s, k.c, d, k.nearc, 3.0e38f, my, BS, wk);
+            if (h.tri >= 0) {
+                TriGeom g = tri_geom(s, h.tri);
+                v3 x = hit_point(g, k.c, d);
+                if (a.aov == 8) aov_values(s, h.tri, g, x, d, v);
+                else v[0] = aov_value(s, a.aov, h.tri, g, x, d);
+                ckt = h.tri;
+                ckx = x;
+            }
+        }
+        if (a.ck_tri) {
+            a.ck_tri[m] = ckt;
+            a.ck_tri[a.M + m] = -1;
+            float* cx = a.ck_x + 3 * (size_t)m;
+            cx[0] = ckx.x; cx[1] = ckx.y; cx[2] = ckx.z;
+            a.ck_vis[m] = 0;
+        }
+    }
+    int nch = a.aov == 8 ? 7 : 1;
+    long npix = (long)a.Ww * (k.y1 - k.y0);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        if (c >= nch) break;
+        float val = v[c] / (float)a.spp;
+        if (reduce) {
+            for (int off = a.spp >> 1; off > 0; off >>= 1) val += __shfl_xor(val, off, BS);
+            if (m < a.M && (lane % a.spp) == 0) image[c * npix + pix] = val;
+        } else if (m < a.M) {
+            atomicAdd(&image[c * npix + pix], val);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // adjoint helpers
 // ---------------------------------------------------------------------------
@@ -282,7 +338,7 @@ __device__ inline void flush_cam(const CamAcc& ca, float* camacc) {
 // ---------------------------------------------------------------------------
 // primary edge samples (eq. mc): one per unit
 // ---------------------------------------------------------------------------
-template <int STK, bool CNT, bool MIX>
+template <int STK, bool CNT, bool MIX, bool AOV = false>
 __device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, const RenderArgs& a, const PEdge* __restrict__ pe,
                                              const double* __restrict__ cdf, const float* __restrict__ d_image,
                                              float* __restrict__ dV, float* __restrict__ camacc, const MixArgs& mx,
@@ -328,16 +384,27 @@ __device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, c
         float dx = Ax - Bx, dy = Ay - By;
         float nl = sqrtf(dx * dx + dy * dy);
         float nx = (Ay - By) / nl, ny = (Bx - Ax) / nl;
-        float fu, fl;
-        radiance_pair(s, rp, 0, k.c, cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny),
-                      k.nearc, true, a.depth, my, BS, wk, fu, fl);
+        v3 du = cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), dl = cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny);
+        int ix = min(max((int)floorf(x), k.x0), k.x1 - 1);
+        int iy = min(max((int)floorf(y), k.y0), k.y1 - 1);
+        const float* dI = d_image + (iy - k.y0) * a.Ww + (ix - k.x0);
+        // loss gradient times the jump of the pixel function across the edge
+        float jump = 0.0f;
+        bool jumps;
+        if (AOV) {
+            jump = aov_jump(s, a.aov, k.c, du, dl, k.nearc, dI, a.Ww * (k.y1 - k.y0), my, BS, wk);
+            jumps = jump != 0.0f;
+        } else {
+            float fu, fl;
+            radiance_pair(s, rp, 0, k.c, du, dl, k.nearc, true, a.depth, my, BS, wk, fu, fl);
+            jumps = fu != fl;
+            if (jumps) jump = dI[0] * (fu - fl);
+        }
         if (m == a.debug_unit)
-            printf("punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g n %.9g %.9g fu %.9g fl %.9g total %.9g\n", m, ei, x,
-                   y, Ax, Ay, Bx, By, nx, ny, fu, fl, total);
-        if (fu != fl) {
-            int ix = min(max((int)floorf(x), k.x0), k.x1 - 1);
-            int iy = min(max((int)floorf(y), k.y0), k.y1 - 1);
-            float w = d_image[(iy - k.y0) * a.Ww + (ix - k.x0)] * (fu - fl) * (float)(inv_p / (double)a.M) / nl;
+            printf("punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g n %.9g %.9g jump %.9g total %.9g\n", m, ei, x, y,
+                   Ax, Ay, Bx, By, nx, ny, jump, total);
+        if (jumps) {
+            float w = jump * (float)(inv_p / (double)a.M) / nl;
             // d alpha / d(a, b) (eq. redner_dirac_jacobian) at the sample point
             float gax = w * (By - y), gay = w * (x - Bx);
             float gbx = w * (y - Ay), gby = w * (Ax - x);
@@ -370,13 +437,13 @@ __device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, c
     flush_cam(ca, camacc);
 }
 
-template <int STK, bool CNT, bool MIX>
+template <int STK, bool CNT, bool MIX, bool AOV = false>
 __global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
                                                 const double* __restrict__ cdf, const float* __restrict__ d_image,
                                                 float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
     __shared__ int stk[STK * BS];
     int sh = blockIdx.x & (a.gshards - 1);
-    primary_body<STK, CNT, MIX>(s, k, a, pe, cdf, d_image, dV + sh * a.gstride, camacc + 12 * sh, mx, blockIdx.x * BS, stk);
+    primary_body<STK, CNT, MIX, AOV>(s, k, a, pe, cdf, d_image, dV + sh * a.gstride, camacc + 12 * sh, mx, blockIdx.x * BS, stk);
 }
 
 // ---------------------------------------------------------------------------
@@ -541,7 +608,9 @@ __device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int 
 // PH: 0 = all in one pass; 1 = rebuild the path, sample the secondary edges and
 // queue their side-path queries; 2 = rebuild the path, read the side
 // radiances of its queries and run the adjoint sweep.
-template <int MAXD, int STK, bool CNT, bool MIX, int PH = 0>
+// AOV (with MAXD = 1, PH = 0): gradient of the geometry-buffer channel a.aov;
+// only the first hit, no NEE, no secondary term.
+template <int MAXD, int STK, bool CNT, bool MIX, int PH = 0, bool AOV = false>
 __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, const RenderArgs& a, const TreeView& tv,
                                               const float* __restrict__ d_image, float* __restrict__ dV,
                                               float* __restrict__ dA, float* __restrict__ camacc, const MixArgs& mx,
@@ -557,7 +626,8 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
     if (PH == 1 && m < a.M)
 #pragma unroll
         for (int kk = 0; kk < MAXD; ++kk) sp.qidx[(size_t)kk * a.M + m] = -1;
-    if (m < a.M && (!a.mask || a.mask[m]) && a.depth >= 1 && a.ck_tri[m] >= 0) {
+    const int depth = AOV ? 1 : a.depth;
+    if (m < a.M && (!a.mask || a.mask[m]) && depth >= 1 && a.ck_tri[m] >= 0) {
         int pix, px, py;
         uint32_t sid;
         unit_pixel(k, a, m, pix, px, py, sid);
@@ -582,17 +652,17 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
             float b = 1.0f;
 #pragma unroll
             for (int kk = 0; kk < MAXD; ++kk) {
-                if (kk >= a.depth) break;
+                if (kk >= depth) break;
                 TriGeom g = tri_geom(s, t);
                 float sgn = dot(d, cross(g.e1, g.e2)) < 0.0f ? 1.0f : -1.0f;
                 v3 n = shading_normal(s, t, g, x) * sgn;
                 float r = s.alb[t];
-                if (r == 0.0f) break;
+                if (r == 0.0f && !AOV) break;
                 tri[kk] = t; xs[kk] = x; ns[kk] = n; sg[kk] = sgn; rho[kk] = r; beta[kk] = b;
                 cc[kk] = 0.0f;
                 wc[kk] = {0, 0, 0};
                 nv = kk + 1;
-                if (kk + 1 >= a.depth) break;
+                if (kk + 1 >= depth) break;
                 float4 ub = rc.block(2 * kk + 2);
                 v3 w = cosine_dir(n, ub.x, ub.y);
                 float c = dot(n, w);
@@ -635,7 +705,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
 #pragma unroll
         for (int kk = 0; kk < MAXD; ++kk) xbar[kk] = {0, 0, 0};
         // ---- secondary boundary term: one edge sample per vertex
-        if ((a.terms & DR_TERM_SECONDARY) && tv.valid) {
+        if ((a.terms & DR_TERM_SECONDARY) && tv.valid && !AOV) {
 #pragma unroll
             for (int kk = 0; kk < MAXD; ++kk) {
                 if (kk >= nv) break;
@@ -748,15 +818,33 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
             if (kk >= nv) continue;
             int t = tri[kk];
             TriGeom g = tri_geom(s, t);
+            v3 gns = {0, 0, 0};
+            v3 gx = xbar[kk] + carry;
+            float Nk = 0.0f;
+            bool cont = false;
+            float Ab = 0.0f;
+            if (AOV) {
+                // d(buffer)/d(position, oriented normal, albedo) at the first hit;
+                // with all channels (aov = 8) their loss gradients are npix apart
+                if (interior) {
+                    float wc7[7];
+                    long npix = (long)a.Ww * (k.y1 - k.y0);
+#pragma unroll
+                    for (int c = 0; c < 7; ++c)
+                        wc7[c] = a.aov == 8 ? d_image[c * npix + pix] / (float)a.spp : (a.aov == c + 1 ? W0 : 0.0f);
+                    gx += v3{wc7[0], wc7[1], wc7[2]};
+                    gns = v3{wc7[3], wc7[4], wc7[5]};
+                    g0[9] = wc7[6];
+                }
+            } else {
             // NEE of this vertex, recomputed from its random numbers; the
             // visibility comes from the forward pass
             NeeSample q = nee_sample(s, rc.block(2 * kk + 1), xs[kk], ns[kk]);
             float Kk = ((vis >> kk) & 1) ? q.K : 0.0f;
             float nee_cos = dot(ns[kk], q.w);
-            float Nk = rho[kk] * nee_cos * Kk;
-            bool cont = cc[kk] > 0.0f;
-            float Ab = cont ? Aft : 0.0f;
-            v3 gns = {0, 0, 0};
+            Nk = rho[kk] * nee_cos * Kk;
+            cont = cc[kk] > 0.0f;
+            Ab = cont ? Aft : 0.0f;
             if (interior) {
                 float gN = W0 * beta[kk];
                 float gw = cont ? W0 * beta[kk] * Ab : 0.0f;
@@ -766,7 +854,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                 gns = q.w * (gN * rho[kk] * Kk);
                 if (cont) gns += wc[kk] * (gw * rho[kk] / cc[kk]);
             }
-            v3 gx = xbar[kk] + carry;
+            }
             v3 gp0 = {0, 0, 0}, gp1 = {0, 0, 0}, gp2 = {0, 0, 0};
             if (gns.x != 0.0f || gns.y != 0.0f || gns.z != 0.0f)
                 shading_normal_adj(s, t, g, xs[kk], gns * sg[kk], gx, gp0, gp1, gp2);
@@ -808,13 +896,13 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
 }
 
 // dL/d(position, look_at, up) from the frame adjoints (f, r, u, c).
-template <int MAXD, int STK, bool CNT, bool MIX>
+template <int MAXD, int STK, bool CNT, bool MIX, bool AOV = false>
 __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs a, TreeView tv, const float* __restrict__ d_image,
                                                  float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc,
                                                  MixArgs mx) {
     __shared__ int stk[STK * BS];
     int sh = blockIdx.x & (a.gshards - 1);
-    backward_body<MAXD, STK, CNT, MIX>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride, camacc + 12 * sh,
+    backward_body<MAXD, STK, CNT, MIX, 0, AOV>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride, camacc + 12 * sh,
                                        mx, blockIdx.x * BS, stk);
 }
 
@@ -1076,6 +1164,7 @@ static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions&
     a.ck_vis = s->ck_vis.as<uint8_t>();
     a.gshards = 1;
     a.gstride = 0;
+    a.aov = o.aov;
     return a;
 }
 
@@ -1089,13 +1178,16 @@ drStatus launch_forward(drScene_t* s, const Cam& cam, const drRenderOptions& o, 
     bool sm = small_stack(s);
     sv.stk_cap = sm ? 32 : kStackDepth;
     bool reduce = (BS % o.spp) == 0;
-    long npix = (long)a.Ww * (cam.y1 - cam.y0);
+    long npix = (long)a.Ww * (cam.y1 - cam.y0) * (o.aov == 8 ? 7 : 1);
     if (!reduce) k_fill<<<nblk(npix, 256), 256, 0, st>>>(image, npix, 0.0f);
     {
         EvScope ev(s, 0, st);
         dim3 g(nblk(a.M, BS)), b(BS);
         int red = reduce ? 1 : 0;
-        if (a.counters) {
+        if (o.aov) {
+            if (sm) k_forward_aov<32><<<g, b, 0, st>>>(sv, cam, a, image, red);
+            else k_forward_aov<kStackDepth><<<g, b, 0, st>>>(sv, cam, a, image, red);
+        } else if (a.counters) {
             if (sm) k_forward<32, true><<<g, b, 0, st>>>(sv, cam, a, image, red);
             else k_forward<kStackDepth, true><<<g, b, 0, st>>>(sv, cam, a, image, red);
         } else {
@@ -1138,7 +1230,7 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
     mx.estats = o.edge_stats;
     mx.plen = s->plen.as<double>();
     bool use_mix = mixing || o.edge_stats;
-    if (use_mix) cbase = nullptr;
+    if (use_mix || o.aov) cbase = nullptr;
     if (o.edge_stats) k_fill<<<nblk(s->E, 256), 256, 0, st>>>(o.edge_stats, s->E, 0.0f);
     if (mx.prim || mx.sec) {
         drStatus r = build_view_mix(s, o.edge_pdf, o.edge_mix, mx.prim != 0, mx.sec != 0, st);
@@ -1153,7 +1245,10 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         const PEdge* pe = s->pe.as<PEdge>();
         const double* pc = s->pcdf.as<double>();
 #define DR_PRIM(S, C, X) k_primary<S, C, X><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx)
-        if (use_mix) {
+        if (o.aov) {
+            if (sm) k_primary<32, false, false, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx);
+            else k_primary<kStackDepth, false, false, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx);
+        } else if (use_mix) {
             if (sm) DR_PRIM(32, false, true);
             else DR_PRIM(kStackDepth, false, true);
         } else if (a.counters) {
@@ -1165,7 +1260,17 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         }
 #undef DR_PRIM
     }
-    if (o.max_depth >= 1) {
+    if (o.aov) {
+        // geometry buffer: interior term at the first hit only
+        TreeView tv{};
+        tv.valid = false;
+        tv.cam = cam.c;
+        EvScope ev(s, 2, st);
+        a.counters = nullptr;
+        dim3 g(nblk(a.M, BS)), b(BS);
+        if (sm) k_backward<1, 32, false, false, true><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx);
+        else k_backward<1, kStackDepth, false, false, true><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx);
+    } else if (o.max_depth >= 1) {
         TreeView tv;
         tv.nodes = s->etree.as<ETNode>();
         tv.valid = (s->n1 + s->n2) > 0 && (terms & DR_TERM_SECONDARY) && s->tree_valid;

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8):
+def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0):
     from paper_1904_12228_amd import api
     x0, y0, x1, y1 = cam.win()
     rng = np.random.default_rng(dimg_seed)
@@ -25,15 +25,17 @@ def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8):
     kw = {}
     if terms:
         kw = dict(interior=bool(terms & 1), primary=bool(terms & 2), secondary=bool(terms & 4))
-    print(f"case: V={scene.num_vertices} T={scene.num_triangles} win={cam.win()} spp={spp} depth={depth} seed={seed}",
-          flush=True)
+    if aov:
+        kw["aov"] = aov
+    print(f"case: V={scene.num_vertices} T={scene.num_triangles} win={cam.win()} spp={spp} depth={depth} seed={seed}"
+          f" aov={aov}", flush=True)
     orc = oracle_reference(scene, cam, spp, depth, seed, dimg, threads=threads, **kw)
     assert orc["stats"][4] == 0, "camera-level near tie in edge classification"
     mask = torch.as_tensor(orc["mask"], device="cuda")
     S = api.Scene(scene)
-    img = S.render(cam, spp, depth, seed, unit_mask=mask)
+    img = S.render(cam, spp, depth, seed, unit_mask=mask, aov=aov)
     dv, da, dc = S.render_backward(cam, spp, depth, torch.as_tensor(dimg, dtype=torch.float32, device="cuda"),
-                                   seed=seed, terms=terms, unit_mask=mask)
+                                   seed=seed, terms=terms, unit_mask=mask, aov=aov)
     torch.cuda.synchronize()
     assert not S.device_error()
     res = dict(img=img.cpu().numpy(), dv=dv.cpu().numpy(), da=da.cpu().numpy(), dc=dc.cpu().numpy())
