@@ -160,6 +160,9 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     s->two_sided = d->emission_two_sided ? 1 : 0;
     s->background = d->background;
     if (const char* e = std::getenv("DIFFRT_SPLIT_BACKWARD")) s->split_backward = std::atoi(e) != 0;
+    // triangle BVH topology: binned SAH on the host (default) or Morton-code LBVH on the device
+    if (const char* e = std::getenv("DIFFRT_BVH")) s->sah_bvh = std::strcmp(e, "lbvh") != 0;
+    s->hI = I;
     if (const char* e = std::getenv("DIFFRT_GRAD_SHARDS")) {
         int k = std::atoi(e);
         if (k >= 1 && k <= 64 && (k & (k - 1)) == 0) s->grad_shards = k;
@@ -273,8 +276,9 @@ drStatus drRenderBackward(drScene s, const drCamera* c, const drRenderOptions* o
         // no matching forward pass: recompute the checkpoints
         r = ensure_checkpoints(s, M);
         if (r != DR_SUCCESS) return r;
+        // the forward writes every channel it renders: seven for aov = 8
         Buf img;
-        if (img.ensure(sizeof(float) * npix) != hipSuccess) return DR_ERROR_OUT_OF_MEMORY;
+        if (img.ensure(sizeof(float) * npix * (o->aov == 8 ? 7 : 1)) != hipSuccess) return DR_ERROR_OUT_OF_MEMORY;
         r = launch_forward(s, cam, *o, img.as<float>(), st);
         (void)hipStreamSynchronize(st);
         img.release();

@@ -256,6 +256,131 @@ __global__ void k_tree_depth(const int* __restrict__ parent, int n, float* __res
     atomicMax(reinterpret_cast<int*>(out), dep);
 }
 
+// Binned-SAH topology of the triangle BVH, built on the host: at each node the
+// centroids of its triangles go into 16 bins per axis and the split between
+// bins with the least surface-area cost (area x count of each child) wins;
+// leaves hold one triangle. Below depth `lim`, and wherever no bin boundary
+// separates the centroids, a node splits at the object median of its widest
+// centroid axis instead, which bounds the depth by lim + log2(T) for any
+// input. Output in the layout of the Morton path: child refs (internal node
+// index, or ~leaf position), parent links (node << 1 | side; internal nodes
+// [0, T-1), leaves [T-1, 2T-1); the root's is -1), triangle per leaf position.
+static void sah_topology(const float* P, const int* I, int T, int lim, std::vector<int>& child,
+                         std::vector<int>& parent, std::vector<int>& order) {
+    constexpr int NB = 16;
+    struct Tb { float lo[3], hi[3], c[3]; };
+    std::vector<Tb> tb(T);
+    for (int t = 0; t < T; ++t) {
+        for (int k = 0; k < 3; ++k) {
+            float a = P[3 * I[3 * t] + k], b = P[3 * I[3 * t + 1] + k], c = P[3 * I[3 * t + 2] + k];
+            tb[t].lo[k] = std::min(a, std::min(b, c));
+            tb[t].hi[k] = std::max(a, std::max(b, c));
+            tb[t].c[k] = (a + b + c) * (1.0f / 3.0f);
+        }
+    }
+    auto area = [](const float lo[3], const float hi[3]) {
+        float d0 = std::max(hi[0] - lo[0], 0.0f), d1 = std::max(hi[1] - lo[1], 0.0f), d2 = std::max(hi[2] - lo[2], 0.0f);
+        return d0 * d1 + d1 * d2 + d2 * d0;
+    };
+    child.assign(2 * (size_t)(T - 1), 0);
+    parent.assign(2 * (size_t)T, -1);
+    order.assign(T, 0);
+    std::vector<int> ids(T);
+    for (int t = 0; t < T; ++t) ids[t] = t;
+    struct Task { int b0, b1, node, depth; };
+    std::vector<Task> stack{{0, T, 0, 0}};
+    int next_node = 1, next_leaf = 0;
+    while (!stack.empty()) {
+        Task k = stack.back();
+        stack.pop_back();
+        int n = k.b1 - k.b0;
+        float clo[3] = {3e38f, 3e38f, 3e38f}, chi[3] = {-3e38f, -3e38f, -3e38f};
+        for (int i = k.b0; i < k.b1; ++i)
+            for (int a = 0; a < 3; ++a) {
+                clo[a] = std::min(clo[a], tb[ids[i]].c[a]);
+                chi[a] = std::max(chi[a], tb[ids[i]].c[a]);
+            }
+        auto bin = [&](int t, int a) {
+            float e = chi[a] - clo[a];
+            int q = (int)((tb[t].c[a] - clo[a]) * ((float)NB / e));
+            return std::min(std::max(q, 0), NB - 1);
+        };
+        int mid = -1;
+        if (k.depth < lim) {
+            int best_a = -1, best_q = -1;
+            float best = 3e38f;
+            for (int a = 0; a < 3; ++a) {
+                if (!(chi[a] > clo[a])) continue;
+                float blo[NB][3], bhi[NB][3];
+                int cnt[NB];
+                for (int q = 0; q < NB; ++q) {
+                    cnt[q] = 0;
+                    for (int j = 0; j < 3; ++j) { blo[q][j] = 3e38f; bhi[q][j] = -3e38f; }
+                }
+                for (int i = k.b0; i < k.b1; ++i) {
+                    int t = ids[i], q = bin(t, a);
+                    ++cnt[q];
+                    for (int j = 0; j < 3; ++j) {
+                        blo[q][j] = std::min(blo[q][j], tb[t].lo[j]);
+                        bhi[q][j] = std::max(bhi[q][j], tb[t].hi[j]);
+                    }
+                }
+                float right[NB];
+                int rc[NB];
+                float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+                int c = 0;
+                for (int q = NB - 1; q >= 1; --q) {
+                    for (int j = 0; j < 3; ++j) { lo[j] = std::min(lo[j], blo[q][j]); hi[j] = std::max(hi[j], bhi[q][j]); }
+                    c += cnt[q];
+                    right[q] = area(lo, hi);
+                    rc[q] = c;
+                }
+                for (int j = 0; j < 3; ++j) { lo[j] = 3e38f; hi[j] = -3e38f; }
+                c = 0;
+                for (int q = 0; q < NB - 1; ++q) {
+                    for (int j = 0; j < 3; ++j) { lo[j] = std::min(lo[j], blo[q][j]); hi[j] = std::max(hi[j], bhi[q][j]); }
+                    c += cnt[q];
+                    if (c == 0 || rc[q + 1] == 0) continue;
+                    float cost = area(lo, hi) * (float)c + right[q + 1] * (float)rc[q + 1];
+                    if (cost < best) { best = cost; best_a = a; best_q = q; }
+                }
+            }
+            if (best_a >= 0) {
+                auto it = std::partition(ids.begin() + k.b0, ids.begin() + k.b1,
+                                         [&](int t) { return bin(t, best_a) <= best_q; });
+                mid = (int)(it - ids.begin());
+                if (mid == k.b0 || mid == k.b1) mid = -1;
+            }
+        }
+        if (mid < 0) {
+            int a = 0;
+            for (int j = 1; j < 3; ++j)
+                if (chi[j] - clo[j] > chi[a] - clo[a]) a = j;
+            mid = k.b0 + n / 2;
+            std::nth_element(ids.begin() + k.b0, ids.begin() + mid, ids.begin() + k.b1, [&](int x, int y) {
+                return tb[x].c[a] < tb[y].c[a] || (tb[x].c[a] == tb[y].c[a] && x < y);
+            });
+        }
+        int range[2][2] = {{k.b0, mid}, {mid, k.b1}};
+        for (int side = 0; side < 2; ++side) {
+            int a = range[side][0], b = range[side][1];
+            int ref;
+            if (b - a == 1) {
+                int pos = next_leaf++;
+                order[pos] = ids[a];
+                parent[T - 1 + pos] = (k.node << 1) | side;
+                ref = ~pos;
+            } else {
+                int nd = next_node++;
+                parent[nd] = (k.node << 1) | side;
+                ref = nd;
+                stack.push_back({a, b, nd, k.depth + 1});
+            }
+            child[2 * (size_t)k.node + side] = ref;
+        }
+    }
+}
+
 drStatus build_scene_static(drScene_t* s, hipStream_t st) {
     const int BS = 256;
     int T = s->T, V = s->V;
@@ -267,7 +392,19 @@ drStatus build_scene_static(drScene_t* s, hipStream_t st) {
                                       s->scal.as<float>());
     k_tri_prep<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->tri.as<float4>());
     k_bounds<<<1, 256, 0, st>>>(s->P.as<float>(), V, s->I.as<int>(), T, s->scal.as<float>());
-    if (T > 1) {
+    if (T > 1 && s->sah_bvh) {
+        // topology on the host from the current vertices; links and boxes on the device
+        s->hP.resize(3 * (size_t)V);
+        DR_CHECK(hipMemcpyAsync(s->hP.data(), s->P.p, sizeof(float) * 3 * V, hipMemcpyDeviceToHost, st));
+        DR_CHECK(hipStreamSynchronize(st));
+        int lg = 0;
+        while ((1 << lg) < T) ++lg;
+        sah_topology(s->hP.data(), s->hI.data(), T, std::max(56 - lg, 0), s->hchild, s->hparent, s->horder);
+        DR_CHECK(hipMemcpyAsync(s->counter.p, s->hchild.data(), sizeof(int) * s->hchild.size(), hipMemcpyHostToDevice, st));
+        DR_CHECK(hipMemcpyAsync(s->parent.p, s->hparent.data(), sizeof(int) * (2 * (size_t)T - 1), hipMemcpyHostToDevice,
+                                st));
+        DR_CHECK(hipMemcpyAsync(s->ids_s.p, s->horder.data(), sizeof(int) * T, hipMemcpyHostToDevice, st));
+    } else if (T > 1) {
         k_morton_tri<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->scal.as<float>(),
                                                    s->codes.as<uint32_t>(), s->ids.as<int>());
         size_t tmp = 0;
@@ -279,6 +416,8 @@ drStatus build_scene_static(drScene_t* s, hipStream_t st) {
         k_keys64<<<blocks(T, BS), BS, 0, st>>>(s->codes_s.as<uint32_t>(), T, s->keys64.as<uint64_t>());
         // child links go to `counter` (int2 per node), then into the nodes; `ids` is reused as refit counters
         k_karras<<<blocks(T - 1, BS), BS, 0, st>>>(s->keys64.as<uint64_t>(), T, s->counter.as<int2>(), s->parent.as<int>());
+    }
+    if (T > 1) {
         k_bvh_links<<<blocks(T - 1, BS), BS, 0, st>>>(s->counter.as<int2>(), T, s->ids_s.as<int>(), s->bvh.as<BvhNode>(),
                                                      s->ids.as<int>());
         k_bvh_refit<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->ids_s.as<int>(),

@@ -61,6 +61,12 @@ struct drScene_t {
     dr::Buf P, I, N, alb, emi, tri, bvh, edges, ekind, lights, lcdf, scal, err;
     // BVH build scratch
     dr::Buf codes, ids, codes_s, ids_s, keys64, parent, counter, sort_tmp;
+    // host side of the SAH build: indices (kept from creation), vertex copy,
+    // child links, parent links, triangle per leaf position
+    bool sah_bvh = true;
+    std::vector<int> hI;
+    std::vector<float> hP;
+    std::vector<int> hchild, hparent, horder;
     // per-view edge data
     dr::Buf pe, plen, pcdf, scan_tmp, ecls, epos, elist, ecode, ecode_s, elist_s, ekeys, eparent, ecounter, etree,
         ebounds, edepth;

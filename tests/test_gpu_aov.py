@@ -92,6 +92,24 @@ def test_all_channels_in_one_pass_equal_the_single_channel_passes(spp):
     S.close()
 
 
+def test_all_channel_backward_recomputes_its_own_forward_pass():
+    # no matching forward pass before the backward: the library re-renders all
+    # seven channels into a buffer of its own
+    from paper_1904_12228_amd import api
+    cfg = sg.soup(seed=3, n_tris=40, width=96, height=80, spp=2)
+    cam = cfg.camera.with_window(20, 15, 67, 52)
+    d = torch.as_tensor(np.random.default_rng(6).normal(size=(7, 37, 47)), dtype=torch.float32, device="cuda")
+    S = api.Scene(cfg.scene)
+    cold = [t.cpu().numpy() for t in S.render_backward(cam, 2, 0, d, seed=5, aov=8)]
+    S.render(cam, 2, 0, seed=5, aov=8)
+    warm = [t.cpu().numpy() for t in S.render_backward(cam, 2, 0, d, seed=5, aov=8)]
+    torch.cuda.synchronize()
+    assert not S.device_error()
+    for a, b in zip(cold, warm):
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * np.abs(b).max())
+    S.close()
+
+
 def test_deferred_shading_of_a_channel_subset():
     from paper_1904_12228_amd import api
     from paper_1904_12228_amd.autograd import gbuffer
