@@ -154,8 +154,8 @@ __device__ inline float radiance(const SceneView& s, const Rng& rng, int base, v
 template <class W>
 __device__ inline void radiance_pair(const SceneView& s, const Rng& rng, int base, v3 o, v3 dp, v3 dm, float tmin,
                                      bool camera, int budget, int* stk, int stride, W& wk, float& Lp, float& Lm) {
-    Hit hp = trace_closest(s, o, dp, tmin, 3.0e38f, stk, stride, wk);
-    Hit hm = trace_closest(s, o, dm, tmin, 3.0e38f, stk, stride, wk);
+    Hit hp, hm;
+    trace_closest2(s, o, dp, dm, tmin, 3.0e38f, stk, stride, wk, hp, hm);
     if (hp.tri == hm.tri) {
         Lp = Lm = 0.0f;
         return;
@@ -194,8 +194,8 @@ __device__ inline void aov_values(const SceneView& s, int tri, const TriGeom& g,
 template <class W>
 __device__ inline float aov_jump(const SceneView& s, int aov, v3 o, v3 dp, v3 dm, float tmin, const float* dI, int npix,
                                  int* stk, int stride, W& wk) {
-    Hit hp = trace_closest(s, o, dp, tmin, 3.0e38f, stk, stride, wk);
-    Hit hm = trace_closest(s, o, dm, tmin, 3.0e38f, stk, stride, wk);
+    Hit hp, hm;
+    trace_closest2(s, o, dp, dm, tmin, 3.0e38f, stk, stride, wk, hp, hm);
     if (hp.tri == hm.tri) return 0.0f;
     if (aov != 8) {
         float Fp = 0.0f, Fm = 0.0f;

@@ -93,6 +93,83 @@ __device__ inline Hit trace_closest(const SceneView& s, v3 o, v3 d, float tmin, 
     return h;
 }
 
+// Closest hits of two rays from one origin (the two sides of a boundary
+// sample, a tiny angle apart) in one traversal: a node is entered when either
+// ray meets one of its boxes (each against its own closest hit so far), a
+// leaf's triangle is fetched once and tested against the rays whose box test
+// passed, and each ray keeps its own closest hit with the same tie rule, so
+// each result equals that ray's own trace_closest.
+template <class W>
+__device__ inline void trace_closest2(const SceneView& s, v3 o, v3 da, v3 db, float tmin, float tmax, int* stk, int stride,
+                                      W& wk, Hit& ha, Hit& hb) {
+    ha = {-1, tmax, 0.0f, 0.0f};
+    hb = {-1, tmax, 0.0f, 0.0f};
+    uint32_t nn = 0, nt = 0;
+    auto consider = [&](int id, bool ta, bool tb) {
+        ++nt;
+        float4 a = s.tri[3 * id], b = s.tri[3 * id + 1], c = s.tri[3 * id + 2];
+        v3 v0 = {a.x, a.y, a.z}, e1 = {a.w, b.x, b.y}, e2 = {b.z, b.w, c.x};
+        auto test = [&](v3 d, Hit& h) {
+            v3 pv = cross(d, e2);
+            float det = dot(e1, pv);
+            if (det == 0.0f) return;
+            float inv = 1.0f / det;
+            v3 tv = o - v0;
+            float u = dot(tv, pv) * inv;
+            if (u < 0.0f || u > 1.0f) return;
+            v3 qv = cross(tv, e1);
+            float v = dot(d, qv) * inv;
+            if (v < 0.0f || u + v > 1.0f) return;
+            float t = dot(e2, qv) * inv;
+            if (t > tmin && (t < h.t || (t == h.t && id < h.tri))) h = {id, t, u, v};
+        };
+        if (ta) test(da, ha);
+        if (tb) test(db, hb);
+    };
+    if (s.T == 1) {
+        consider(0, true, true);
+        wk.ray(0, nt);
+        wk.ray(0, 0);
+        return;
+    }
+    const float kInf = __builtin_huge_valf();
+    RayInv ra = ray_inv(o, da), rb = ray_inv(o, db);
+    int sp = 0;
+    int node = 0;
+    int guard = 2 * s.T + 8;
+    while (true) {
+        if (--guard < 0) { atomicOr(s.err, kErrStack); break; }
+        ++nn;
+        BvhNode n = s.bvh[node];
+        float tla, tra, tlb, trb;
+        bool hla = slab(ra, n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, tmin, ha.t, tla);
+        bool hra = slab(ra, n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w, tmin, ha.t, tra);
+        bool hlb = slab(rb, n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, tmin, hb.t, tlb);
+        bool hrb = slab(rb, n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w, tmin, hb.t, trb);
+        int l = n.d.x, rr = n.d.y;
+        if ((hla || hlb) && l < 0) { consider(~l, hla, hlb); hla = hlb = false; }
+        if ((hra || hrb) && rr < 0) { consider(~rr, hra, hrb); hra = hrb = false; }
+        bool hl = hla || hlb, hr = hra || hrb;
+        if (hl && hr) {
+            float tl = fminf(hla ? tla : kInf, hlb ? tlb : kInf), tr = fminf(hra ? tra : kInf, hrb ? trb : kInf);
+            int nearc = tl <= tr ? l : rr, farc = tl <= tr ? rr : l;
+            if (sp < s.stk_cap) stk[(sp++) * stride] = farc;
+            else atomicOr(s.err, kErrStack);
+            node = nearc;
+        } else if (hl) {
+            node = l;
+        } else if (hr) {
+            node = rr;
+        } else {
+            if (sp == 0) break;
+            node = stk[(--sp) * stride];
+        }
+    }
+    // one traversal, two rays
+    wk.ray(nn, nt);
+    wk.ray(0, 0);
+}
+
 // Any hit in (tmin, tmax).
 template <class W>
 __device__ inline bool trace_any(const SceneView& s, v3 o, v3 d, float tmin, float tmax, int* stk, int stride, W& wk) {
