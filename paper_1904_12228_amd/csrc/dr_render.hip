@@ -437,8 +437,10 @@ __device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, c
     flush_cam(ca, camacc);
 }
 
+// Five waves per SIMD (at most 96 VGPRs, a few spilled): measured faster
+// than four for this kernel, unlike for the path backward kernels.
 template <int STK, bool CNT, bool MIX, bool AOV = false>
-__global__ __launch_bounds__(BS) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
+__global__ __launch_bounds__(BS, 5) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
                                                 const double* __restrict__ cdf, const float* __restrict__ d_image,
                                                 float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
     __shared__ int stk[STK * BS];

@@ -81,3 +81,24 @@ def test_invalid_arguments_are_rejected():
                          np.zeros(len(idx), np.float32))
         with pytest.raises(_lib.DiffrtError):
             api.Scene(scene)
+
+
+def test_sah_and_morton_bvh_give_the_same_results(monkeypatch):
+    # the BVH only decides which triangles are tested; closest hits, images
+    # and gradients do not depend on it (up to the order of atomic additions)
+    from paper_1904_12228_amd import api
+    cfg = sg.sphere_box(seed=1, level=3, width=48, height=48, spp=2, max_depth=3)
+    d = torch.as_tensor(np.random.default_rng(9).normal(size=(48, 48)), dtype=torch.float32, device="cuda")
+    res = []
+    for kind in ("sah", "lbvh"):
+        monkeypatch.setenv("DIFFRT_BVH", kind)
+        S = api.Scene(cfg.scene)
+        img = S.render(cfg.camera, 2, 3, seed=4)
+        g = S.render_backward(cfg.camera, 2, 3, d, seed=4)
+        res.append([img.cpu().numpy()] + [t.cpu().numpy() for t in g])
+        assert not S.device_error()
+        S.close()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(res[0][0], res[1][0], rtol=1e-6, atol=1e-7)
+    for a, b in zip(res[0][1:], res[1][1:]):
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * np.abs(b).max())
