@@ -128,10 +128,17 @@ typedef struct {
 
 /* Creates a scene: validates sizes and indices (host copy of the topology),
  * extracts unique edges (sorted by (min vertex, max vertex)), builds the
- * triangle BVH. Synchronises `stream`. */
+ * triangle BVH (binned-SAH topology on the host, boxes on the device; with
+ * the environment variable DIFFRT_BVH=lbvh a Morton-code LBVH built on the
+ * device). Non-finite vertex coordinates are rejected with
+ * DR_ERROR_INVALID_VALUE. Synchronises `stream`. */
 drStatus drSceneCreate(drScene* out, const drSceneDesc* desc, hipStream_t stream);
 
-/* Replaces all vertex positions ([V][3] device) and rebuilds the BVH. */
+/* Replaces all vertex positions ([V][3] device) and rebuilds the BVH as
+ * drSceneCreate does (synchronises `stream`; for optimisation loops that must
+ * not synchronise, drSceneRefit keeps the topology). On
+ * DR_ERROR_INVALID_VALUE (non-finite coordinates) the scene may only be
+ * updated again or destroyed. */
 drStatus drSceneUpdateVertices(drScene scene, const float* vertices, hipStream_t stream);
 
 /* Replaces all triangle albedos ([T] device, in [0, 1]) for material

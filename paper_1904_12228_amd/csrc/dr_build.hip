@@ -397,6 +397,8 @@ drStatus build_scene_static(drScene_t* s, hipStream_t st) {
         s->hP.resize(3 * (size_t)V);
         DR_CHECK(hipMemcpyAsync(s->hP.data(), s->P.p, sizeof(float) * 3 * V, hipMemcpyDeviceToHost, st));
         DR_CHECK(hipStreamSynchronize(st));
+        for (float x : s->hP)
+            if (!std::isfinite(x)) return DR_ERROR_INVALID_VALUE;   // no meaningful bounds or splits
         int lg = 0;
         while ((1 << lg) < T) ++lg;
         sah_topology(s->hP.data(), s->hI.data(), T, std::max(56 - lg, 0), s->hchild, s->hparent, s->horder);

@@ -74,6 +74,12 @@ def test_invalid_arguments_are_rejected():
         S.render_backward(cam, 4, 0, torch.zeros((cam.height, cam.width), device="cuda"), edge_mix=1.0,
                           edge_pdf=torch.full((S.num_edges,), 1.0 / S.num_edges, device="cuda"))
     S.close()
+    # a non-finite vertex coordinate
+    cfg2 = sg.soup(seed=3, n_tris=20, width=32, height=32, spp=2)
+    bad = cfg2.scene.copy()
+    bad.vertices[5, 1] = np.nan
+    with pytest.raises(_lib.DiffrtError):
+        api.Scene(bad)
     # a triangle repeating a vertex, and an edge shared by three triangles
     v = np.array([[0, 0, 1], [1, 0, 1], [0, 1, 1], [1, 1, 1], [0.5, 0.5, 2]], np.float32)
     for idx in ([[0, 1, 1]], [[0, 1, 2], [0, 1, 3], [0, 1, 4]]):
