@@ -242,8 +242,8 @@ drStatus drSceneGetInfo(drScene s, int32_t* nv, int32_t* nt, int32_t* ne) {
 }
 
 static drStatus ensure_checkpoints(drScene s, long M) {
-    if (s->ck_tri.ensure(sizeof(int) * 2 * (size_t)M) != hipSuccess ||
-        s->ck_x.ensure(sizeof(float) * 6 * (size_t)M) != hipSuccess || s->ck_vis.ensure((size_t)M) != hipSuccess)
+    if (s->ck_tri.ensure(sizeof(int) * 3 * (size_t)M) != hipSuccess ||
+        s->ck_x.ensure(sizeof(float) * 9 * (size_t)M) != hipSuccess || s->ck_vis.ensure((size_t)M) != hipSuccess)
         return DR_ERROR_OUT_OF_MEMORY;
     return DR_SUCCESS;
 }

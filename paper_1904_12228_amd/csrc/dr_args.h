@@ -15,8 +15,8 @@ struct RenderArgs {
     unsigned long long* counters;   // [5] work counters, or null
     uint32_t k0, k1, view, terms;
     const uint8_t* mask;
-    int* ck_tri;       // [2][M]
-    float* ck_x;       // [2][M][3]
+    int* ck_tri;       // [3][M] triangle at path vertices 0, 1, 2 (-1: none)
+    float* ck_x;       // [3][M][3] their positions
     uint8_t* ck_vis;   // [M]
     // gradient shards: block b adds into copy (b & (gshards - 1)) of the
     // gradient arrays (gstride floats apart) and of the camera accumulator
@@ -52,7 +52,7 @@ struct SplitArgs {
     float2* res;                 // [cap] (radiance on the + side, on the - side)
     int* qidx;                   // [MAXD][M] query of (vertex, unit), -1 if none
     int* count;                  // [MAXD] queries appended per path vertex (segment kk starts at kk * M)
-    int* vtri;                   // [MAXD - 2][M] triangle hit by traced path vertex kk + 1 >= 2 (-1: miss)
+    int* vtri;                   // [MAXD - 2][M] triangle hit by traced path vertex kk + 1 >= 3, slot kk - 1 (-1: miss)
     float* vx;                   // [MAXD - 2][M][3] its position
 };
 

@@ -80,8 +80,8 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
     }
     b->total_blocks = boff[n];
     long MT = ck_off[n];
-    B_ALLOC(b->ck_tri, sizeof(int) * 2 * (size_t)MT);
-    B_ALLOC(b->ck_x, sizeof(float) * 6 * (size_t)MT);
+    B_ALLOC(b->ck_tri, sizeof(int) * 3 * (size_t)MT);
+    B_ALLOC(b->ck_x, sizeof(float) * 9 * (size_t)MT);
     B_ALLOC(b->ck_vis, (size_t)MT);
     B_ALLOC(b->pe, sizeof(PEdge) * (size_t)n * E);
     B_ALLOC(b->pcdf, sizeof(double) * (size_t)n * (E + 1));
@@ -141,8 +141,8 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
         a.counters = nullptr;
         a.mask = nullptr;
         a.debug_unit = -1;
-        a.ck_tri = b->ck_tri.as<int>() + 2 * ck_off[v];
-        a.ck_x = b->ck_x.as<float>() + 6 * ck_off[v];
+        a.ck_tri = b->ck_tri.as<int>() + 3 * ck_off[v];
+        a.ck_x = b->ck_x.as<float>() + 9 * ck_off[v];
         a.ck_vis = b->ck_vis.as<uint8_t>() + ck_off[v];
         BatchView& bv = hv[v];
         bv.k = cam;

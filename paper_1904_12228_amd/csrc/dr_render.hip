@@ -60,8 +60,8 @@ __device__ __forceinline__ void forward_body(const SceneView& s, const Cam& k, c
         uint32_t sid;
         unit_pixel(k, a, m, pix, px, py, sid);
         bool act = !a.mask || a.mask[m];
-        int ckt0 = -1, ckt1 = -1;
-        v3 ckx0 = {0, 0, 0}, ckx1 = {0, 0, 0};
+        int ckt0 = -1, ckt1 = -1, ckt2 = -1;
+        v3 ckx0 = {0, 0, 0}, ckx1 = {0, 0, 0}, ckx2 = {0, 0, 0};
         uint8_t vis = 0;
         if (act) {
             Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
@@ -101,16 +101,20 @@ __device__ __forceinline__ void forward_body(const SceneView& s, const Cam& k, c
                     x = hit_point(g, x, w);
                     front = dot(w, cross(g.e1, g.e2)) < 0.0f;
                     if (kk == 1) { ckt1 = tri; ckx1 = x; }
+                    if (kk == 2) { ckt2 = tri; ckx2 = x; }
                 }
             }
         }
         if (a.ck_tri) {
             a.ck_tri[m] = ckt0;
             a.ck_tri[a.M + m] = ckt1;
+            a.ck_tri[2 * (size_t)a.M + m] = ckt2;
             float* cx = a.ck_x + 3 * (size_t)m;
             cx[0] = ckx0.x; cx[1] = ckx0.y; cx[2] = ckx0.z;
             float* cy = a.ck_x + 3 * ((size_t)a.M + m);
             cy[0] = ckx1.x; cy[1] = ckx1.y; cy[2] = ckx1.z;
+            float* cz = a.ck_x + 3 * (2 * (size_t)a.M + m);
+            cz[0] = ckx2.x; cz[1] = ckx2.y; cz[2] = ckx2.z;
             a.ck_vis[m] = vis;
         }
     }
@@ -167,6 +171,7 @@ __global__ __launch_bounds__(BS) void k_forward_aov(SceneView s, Cam k, RenderAr
         if (a.ck_tri) {
             a.ck_tri[m] = ckt;
             a.ck_tri[a.M + m] = -1;
+            a.ck_tri[2 * (size_t)a.M + m] = -1;
             float* cx = a.ck_x + 3 * (size_t)m;
             cx[0] = ckx.x; cx[1] = ckx.y; cx[2] = ckx.z;
             a.ck_vis[m] = 0;
@@ -671,10 +676,11 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                 if (c <= 0.0f) break;
                 int t2;
                 v3 x2;
-                if (kk + 1 < 2) {
-                    t2 = a.ck_tri[a.M + m];
+                if (kk + 1 < 3) {
+                    // vertices 1 and 2 were stored by the forward pass
+                    t2 = a.ck_tri[(size_t)(kk + 1) * a.M + m];
                     if (t2 < 0) break;
-                    const float* cx = a.ck_x + 3 * ((size_t)a.M + m);
+                    const float* cx = a.ck_x + 3 * ((size_t)(kk + 1) * a.M + m);
                     x2 = {cx[0], cx[1], cx[2]};
                 } else if (PH == 2) {
                     // the sampling pass traced this vertex: take its hit
@@ -1288,7 +1294,7 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         int maxd = o.max_depth <= 1 ? 1 : (o.max_depth <= 3 ? 3 : 6);
         if (split) {
             size_t cap = (size_t)maxd * (size_t)a.M;
-            // traced vertices 2 .. MAXD-1 (path vertex index kk + 1 >= 2, slot kk - 1)
+            // traced vertices 3 .. MAXD-1 (path vertex index kk + 1 >= 3, slot kk - 1; slot 0 unused)
             size_t vcap = (size_t)std::max(maxd - 2, 1) * (size_t)a.M;
             if (s->sq.ensure(sizeof(SideQuery) * cap) != hipSuccess || s->sres.ensure(sizeof(float2) * cap) != hipSuccess ||
                 s->sqidx.ensure(sizeof(int) * cap) != hipSuccess || s->scount.ensure(sizeof(int) * 6) != hipSuccess ||
