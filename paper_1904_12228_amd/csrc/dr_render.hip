@@ -821,6 +821,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
         float Aft = 0.0f;          // radiance from later vertices per unit throughput there
         v3 carry = {0, 0, 0};      // adjoint of this vertex's position from the next ray-plane
         v3 gd0 = {0, 0, 0};
+        float grho_k = 0.0f;       // albedo adjoint of vertices 2.. (scattered with their vertices)
 #pragma unroll
         for (int kk = MAXD - 1; kk >= 0; --kk) {
             if (kk >= nv) continue;
@@ -858,7 +859,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                 float gw = cont ? W0 * beta[kk] * Ab : 0.0f;
                 float grho = gN * nee_cos * Kk + gw;
                 if (kk == 0) g0[9] = grho;
-                else if (grho != 0.0f) atomicAdd(&dA[t], grho);
+                else grho_k = grho;
                 gns = q.w * (gN * rho[kk] * Kk);
                 if (cont) gns += wc[kk] * (gw * rho[kk] / cc[kk]);
             }
@@ -876,11 +877,21 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                 g0[0] = gp0.x; g0[1] = gp0.y; g0[2] = gp0.z;
                 g0[3] = gp1.x; g0[4] = gp1.y; g0[5] = gp1.z;
                 g0[6] = gp2.x; g0[7] = gp2.y; g0[8] = gp2.z;
+            } else if (__ballot(1) == ~0ull) {
+                // every lane of the wave is at this vertex: lanes that hit the
+                // same triangle (large walls, say) are summed before the atomics
+                const float gv[10] = {gp0.x, gp0.y, gp0.z, gp1.x, gp1.y, gp1.z, gp2.x, gp2.y, gp2.z, grho_k};
+                scatter_grouped(true, t, gv, 4, [&](int tt, int i) {
+                    return i == 9 ? &dA[tt] : &dV[3 * s.I[3 * tt + i / 3] + (i % 3)];
+                });
+                grho_k = 0.0f;
             } else {
                 int i0 = s.I[3 * t], i1 = s.I[3 * t + 1], i2 = s.I[3 * t + 2];
                 atomic_add3(dV, i0, gp0);
                 atomic_add3(dV, i1, gp1);
                 atomic_add3(dV, i2, gp2);
+                if (grho_k != 0.0f) atomicAdd(&dA[t], grho_k);
+                grho_k = 0.0f;
             }
             wk.atomics(10);
             if (kk == 0) {
