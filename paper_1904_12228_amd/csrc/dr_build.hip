@@ -301,8 +301,9 @@ static void sah_topology(const float* P, const int* I, int T, int lim, std::vect
                 chi[a] = std::max(chi[a], tb[ids[i]].c[a]);
             }
         auto bin = [&](int t, int a) {
+            // (c - lo) / extent lies in [0, 1]: no overflow however small the extent
             float e = chi[a] - clo[a];
-            int q = (int)((tb[t].c[a] - clo[a]) * ((float)NB / e));
+            int q = (int)((tb[t].c[a] - clo[a]) / e * (float)NB);
             return std::min(std::max(q, 0), NB - 1);
         };
         int mid = -1;
