@@ -262,6 +262,21 @@ drStatus drMlpSoftmaxXent(const float* logits, const float* target, const int32_
 drStatus drMlpBackward(const float* theta, const float* x, int32_t n, const float* d_logits, float* grad,
                        hipStream_t stream);
 
+/* drMlpSoftmaxXent without the caller's scratch argument and without any
+ * device allocation, for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc). The per-view
+ * target sums live in a fixed device array of DR_XENT_MAX_VIEWS floats
+ * (256 KiB) that the library holds on each GPU it runs on until the process
+ * ends; the stream must belong to the current device. Arguments and results
+ * are those of drMlpSoftmaxXent. Errors: n_views > DR_XENT_MAX_VIEWS (or any
+ * argument drMlpSoftmaxXent rejects) gives DR_ERROR_INVALID_VALUE; failing to
+ * resolve the array's device address gives DR_ERROR_DEVICE. All calls on one
+ * GPU share the array: calls whose work overlaps on that GPU (different
+ * streams, no ordering) race and give undefined results. */
+#define DR_XENT_MAX_VIEWS 65536
+drStatus drMlpSoftmaxXentNoAlloc(const float* logits, const float* target, const int32_t* offsets, int32_t n_views,
+                                 float* prob, float* d_logits, float* view_loss, hipStream_t stream);
+
 /* drAdamStep with the step count in device memory (*step = steps taken so
  * far, int64, incremented by this call): for optimisation steps captured in a
  * HIP graph, whose launch arguments are fixed at capture. */

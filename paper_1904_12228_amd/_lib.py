@@ -22,7 +22,7 @@ EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneUpdateAlbedo", "drS
            "drRenderBackward", "drAdamStep", "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy",
            "drGetErrorString", "drEdgeFeatures", "drMlpForward", "drMlpSoftmaxXent", "drMlpBackward",
            "drSceneRefit", "drBatchCreate", "drBatchRefit", "drBatchAdvanceSeed", "drBatchForward", "drBatchBackward",
-           "drBatchSetLaunch", "drBatchDestroy", "drAdamStepCounted"]
+           "drBatchSetLaunch", "drBatchDestroy", "drAdamStepCounted", "drMlpSoftmaxXentNoAlloc"]
 
 MLP_PARAMS = 6337
 EDGE_FEATURES = 32
@@ -100,6 +100,7 @@ def load():
         "drBatchSetLaunch": [vp, i32, i32],
         "drBatchDestroy": [vp],
         "drAdamStepCounted": [vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, vp, vp],
+        "drMlpSoftmaxXentNoAlloc": [vp, vp, vp, i32, vp, vp, vp, vp],
     }
     assert set(sig) == set(EXPORTS), sorted(set(EXPORTS) ^ set(sig))
     for name, args in sig.items():

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "dr_host.h"
 
@@ -446,6 +447,30 @@ __global__ void k_zero(float* __restrict__ x, int n) {
 
 int grid_for(int tiles, int cap) { return tiles < 1 ? 1 : (tiles < cap ? tiles : cap); }
 
+// Per-view target sums of drMlpSoftmaxXentNoAlloc: one device-resident array
+// per GPU, held until the process ends. In host code the name stands for a
+// host-side shadow, not a device address: kernels and copies take the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float xent_scratch[DR_XENT_MAX_VIEWS];
+
+constexpr int kMaxDevices = 64;
+std::mutex xent_mu;
+float* xent_ptr[kMaxDevices] = {};
+
+// Device address of xent_scratch on the current device (looked up once per
+// device, with that device current), or nullptr on failure.
+float* xent_scratch_ptr() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(xent_mu);
+    if (!xent_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(xent_scratch)) != hipSuccess || !p) return nullptr;
+        xent_ptr[dev] = static_cast<float*>(p);
+    }
+    return xent_ptr[dev];
+}
+
 }  // namespace
 }  // namespace dr
 
@@ -483,6 +508,22 @@ extern "C" drStatus drMlpSoftmaxXent(const float* logits, const float* target, c
     if (!logits || !offsets || n_views < 0 || (n_views > 0 && !scratch) || ((d_logits || view_loss) && !target))
         return DR_ERROR_INVALID_VALUE;
     if (n_views == 0) return DR_SUCCESS;
+    if (target) k_view_target_sum<<<n_views, 256, 0, st>>>(target, offsets, scratch);
+    else k_zero<<<(n_views + 255) / 256, 256, 0, st>>>(scratch, n_views);
+    k_softmax_xent<<<n_views, 256, 0, st>>>(logits, target, offsets, n_views, scratch, prob, d_logits, view_loss);
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+extern "C" drStatus drMlpSoftmaxXentNoAlloc(const float* logits, const float* target, const int32_t* offsets,
+                                            int32_t n_views, float* prob, float* d_logits, float* view_loss,
+                                            hipStream_t st) {
+    if (!logits || !offsets || n_views < 0 || n_views > DR_XENT_MAX_VIEWS || ((d_logits || view_loss) && !target))
+        return DR_ERROR_INVALID_VALUE;
+    if (n_views == 0) return DR_SUCCESS;
+    float* scratch = xent_scratch_ptr();
+    if (!scratch) return DR_ERROR_DEVICE;
+    // every entry the softmax reads, [0, n_views), is written first by one of
+    // these two kernels: nothing left by an earlier call is used
     if (target) k_view_target_sum<<<n_views, 256, 0, st>>>(target, offsets, scratch);
     else k_zero<<<(n_views + 255) / 256, 256, 0, st>>>(scratch, n_views);
     k_softmax_xent<<<n_views, 256, 0, st>>>(logits, target, offsets, n_views, scratch, prob, d_logits, view_loss);
