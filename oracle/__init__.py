@@ -48,7 +48,8 @@ class _Options(C.Structure):
                 ("secondary_edges", C.c_int32), ("use_bvh", C.c_int32), ("exclude_flagged", C.c_int32),
                 ("num_threads", C.c_int32), ("unit_mask", C.c_void_p),
                 ("dir_mode", C.c_int32), ("dir_log", C.c_void_p),
-                ("edge_pdf", C.c_void_p), ("mix", C.c_double), ("mix_terms", C.c_int32), ("aov", C.c_int32)]
+                ("edge_pdf", C.c_void_p), ("mix", C.c_double), ("mix_terms", C.c_int32), ("aov", C.c_int32),
+                ("edge_t_mode", C.c_int32)]
 
 
 class _Outputs(C.Structure):
@@ -72,6 +73,8 @@ def lib():
         _lib.orc_closest_hit.restype = C.c_int
         _lib.orc_edge_tree_pdf.restype = C.c_int
         _lib.orc_edge_tree_sample.restype = C.c_int
+        _lib.orc_edge_t_cosine.restype = C.c_int
+        _lib.orc_edge_t_cosine_pdf.restype = C.c_double
     return _lib
 
 
@@ -118,13 +121,14 @@ def _camera_struct(cam, keep=None, params64=None):
 def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, primary=True,
            secondary=True, use_bvh=True, exclude_flagged=False, threads=1, unit_mask=None,
            view_id=0, want_flags=False, vertices64=None, albedo64=None, camera64=None,
-           dir_mode=0, dir_log=None, edge_pdf=None, mix=0.0, mix_terms=3, edge_stats=False, aov=0):
+           dir_mode=0, dir_log=None, edge_pdf=None, mix=0.0, mix_terms=3, edge_stats=False, aov=0, edge_t=0):
     """Returns a dict with image, (if d_image) d_vertices, d_albedo, d_camera,
     the matching mass arrays, unit flags and stats; with edge_stats=True also
     the per-edge harvest statistic. edge_pdf (a distribution over all edges)
     and mix in [0, 1) select the proposal mixture (mix_terms: bit 0 primary,
     bit 1 secondary). aov selects a geometry buffer instead of radiance
-    (1-3 position, 4-6 shading normal, 7 albedo)."""
+    (1-3 position, 4-6 shading normal, 7 albedo). edge_t = 1 draws the point
+    on each secondary edge by the clamped cosine instead of uniformly."""
     keep = []
     s = _scene_struct(scene, keep, vertices64, albedo64)
     c = _camera_struct(cam, keep, camera64)
@@ -137,7 +141,7 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
     q = None if edge_pdf is None else np.ascontiguousarray(edge_pdf, np.float64)
     o = _Options(spp, max_depth, seed, view_id, int(interior), int(primary), int(secondary),
                  int(use_bvh), int(exclude_flagged), threads, _ptr(mask), int(dir_mode), _ptr(dir_log),
-                 _ptr(q), float(mix), int(mix_terms), int(aov))
+                 _ptr(q), float(mix), int(mix_terms), int(aov), int(edge_t))
     res = {"image": np.zeros((Hw, Ww), np.float64), "stats": np.zeros(8, np.int64)}
     if d_image is not None:
         dimg = np.ascontiguousarray(np.broadcast_to(np.asarray(d_image, np.float64), (Hw, Ww)))
@@ -273,3 +277,19 @@ def secondary_forms(p, v0, v1, t, m0, nm):
     lib().orc_secondary_forms(_vp(arr[0]), _vp(arr[1]), _vp(arr[2]), C.c_double(t), _vp(arr[3]),
                               _vp(arr[4]), _vp(af), _vp(df))
     return af.reshape(3, 3), df.reshape(3, 3)
+
+
+def edge_t_cosine(p, n, v0, v1, u):
+    """Clamped-cosine edge-point sampler: (t, pdf_t) per uniform in u (t = -1
+    where there is no sample)."""
+    u = np.ascontiguousarray(u, np.float64)
+    t = np.zeros(u.size)
+    pt = np.zeros(u.size)
+    args = [np.ascontiguousarray(x, np.float64) for x in (p, n, v0, v1)]
+    lib().orc_edge_t_cosine(*[_vp(a) for a in args], int(u.size), _vp(u), _vp(t), _vp(pt))
+    return t, pt
+
+
+def edge_t_cosine_pdf(p, n, v0, v1, t):
+    args = [np.ascontiguousarray(x, np.float64) for x in (p, n, v0, v1)]
+    return float(lib().orc_edge_t_cosine_pdf(*[_vp(a) for a in args], C.c_double(t)))

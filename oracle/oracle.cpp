@@ -1194,6 +1194,83 @@ S aov_impl(const Env<S>& E, Unit& U, int aov, const V3<S>& o, const V3<S>& d0, d
 }
 
 // ---------------------------------------------------------------------------
+// Point on a secondary edge drawn in proportion to the clamped cosine (Ch. 5,
+// Importance sampling on an edge: the thesis samples an edge point by the
+// shading lobe integrated along the edge; for a Lambertian surface the lobe is
+// the clamped cosine itself).
+//
+// Seen from p the edge is a great-circle arc of directions: w(phi) = cos(phi)
+// a + sin(phi) b', phi in [0, Phi], a toward v0, b' the unit vector in the
+// arc's plane orthogonal to a, Phi the angle between the directions to v0 and
+// v1. Along it n . w(phi) = R cos(phi - phi0), so the integral of its positive
+// part over [lo, phi] is R (sin(phi - phi0) - sin(lo - phi0)), with [lo, hi]
+// the part of [0, Phi] where the cosine is positive; the inverse of its
+// normalised integral is an arcsine. The drawn direction is mapped to the edge
+// parameter t (the point of the edge line along it), and the density in t is
+// the density in phi times the arc-length Jacobian |e x w^| / |w|:
+//   p(t) = max(n . w^(t), 0) |e x w^(t)| / (T |w(t)|),  T = integral of the
+//   positive part of the cosine over the whole arc.
+// Returns false (no sample) when T is zero or the arc degenerate.
+// ---------------------------------------------------------------------------
+const double kArcMin = 1e-6;      // sin of the smallest arc the cosine sampler handles
+const double kTieArc = 1e-5;      // relative closeness of the arc test and of T to zero
+
+bool cosine_edge_t(V3d p, V3d n, V3d pa, V3d pb, double u, double& t, bool* flag) {
+    V3d a = normalize(pa - p), b = normalize(pb - p);
+    double cab = dot(a, b);
+    V3d bo = b - a * cab;
+    double sb = length(bo);
+    if (flag && std::fabs(sb - kArcMin) < kTieArc * kArcMin) *flag = true;
+    if (!(sb > kArcMin)) return false;
+    bo = bo / sb;
+    double Phi = std::atan2(sb, cab);
+    double A = dot(n, a), B = dot(n, bo);
+    double phi0 = std::atan2(B, A);
+    if (phi0 < -kPi / 2) phi0 += 2 * kPi;
+    double lo = std::max(0.0, phi0 - kPi / 2), hi = std::min(Phi, phi0 + kPi / 2);
+    if (flag && std::fabs(hi - lo) < kTieArc) *flag = true;
+    if (!(hi > lo)) return false;
+    double slo = std::sin(lo - phi0), shi = std::sin(hi - phi0);
+    double sv = slo + u * (shi - slo);
+    double phi = phi0 + std::asin(std::max(-1.0, std::min(1.0, sv)));
+    V3d wd = a * std::cos(phi) + bo * std::sin(phi);
+    V3d e = pb - pa, v0p = pa - p;
+    V3d ew = cross(e, wd);
+    t = -dot(cross(v0p, wd), ew) / dot(ew, ew);
+    t = std::max(0.0, std::min(1.0, t));
+    return true;
+}
+
+// T of cosine_edge_t: the integral over the arc of the positive part of the cosine.
+double cosine_arc_integral(V3d p, V3d n, V3d pa, V3d pb) {
+    V3d a = normalize(pa - p), b = normalize(pb - p);
+    double cab = dot(a, b);
+    V3d bo = b - a * cab;
+    double sb = length(bo);
+    if (!(sb > kArcMin)) return 0;
+    bo = bo / sb;
+    double Phi = std::atan2(sb, cab);
+    double A = dot(n, a), B = dot(n, bo);
+    double R = std::hypot(A, B);
+    double phi0 = std::atan2(B, A);
+    if (phi0 < -kPi / 2) phi0 += 2 * kPi;
+    double lo = std::max(0.0, phi0 - kPi / 2), hi = std::min(Phi, phi0 + kPi / 2);
+    if (!(hi > lo)) return 0;
+    return R * (std::sin(hi - phi0) - std::sin(lo - phi0));
+}
+
+// Density in t of cosine_edge_t at edge parameter t.
+double cosine_edge_pdf(V3d p, V3d n, V3d pa, V3d pb, double t, double T) {
+    V3d e = pb - pa;
+    V3d w = pa + e * t - p;
+    double wl = length(w);
+    V3d wh = w / wl;
+    double c = dot(n, wh);
+    if (!(c > 0) || !(T > 0)) return 0;
+    return c * length(cross(e, wh)) / (T * wl);
+}
+
+// ---------------------------------------------------------------------------
 // Per-unit evaluation
 // ---------------------------------------------------------------------------
 struct Ctx {
@@ -1332,7 +1409,15 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 if (e.f0 == pv.tri || e.f1 == pv.tri) continue;
                 if (!disc_from(s, e, p, &U.flag)) continue;
                 V3d pa = s.p(e.va), pb = s.p(e.vb);
-                V3d vt = pa + (pb - pa) * b0[1];
+                // the point on the edge: uniform in t, or by the clamped cosine
+                double te = b0[1], pdf_t = 1.0;
+                if (o.edge_t_mode == 1) {
+                    if (!cosine_edge_t(p, nsv, pa, pb, b0[1], te, &U.flag)) continue;
+                    double Tc = cosine_arc_integral(p, nsv, pa, pb);
+                    pdf_t = cosine_edge_pdf(p, nsv, pa, pb, te, Tc);
+                    if (!(pdf_t > 0)) continue;
+                }
+                V3d vt = pa + (pb - pa) * te;
                 V3d w = vt - p;
                 if (dot(nsv, w) <= kHorizon * s.diag) continue;
                 V3d v0p = pa - p, v1p = pb - p;
@@ -1362,11 +1447,12 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 used_s++;
                 if (Fp == Fm) continue;
                 double W = C.d_image[pix] * val(pv.beta) / C.spp;
-                double wgt = W * (Fp - Fm) * length(cross(pb - pa, wh)) / (cn * wl * pdf);
+                double wgt = W * (Fp - Fm) * length(cross(pb - pa, wh)) / (cn * wl * pdf * pdf_t);
                 if (dbg)
                     std::fprintf(stderr, "unit %d vertex %d tri %d p=(%.9g %.9g %.9g) n=(%.9g %.9g %.9g) edge %d pdf %.9g "
-                                 "t %.9g Lp %.9g Lm %.9g cos %.9g W %.9g wgt %.9g kappa %.3g\n",
-                                 m, k, pv.tri, p.x, p.y, p.z, nsv.x, nsv.y, nsv.z, ei, pdf, b0[1], Lp, Lm, cosw, W, wgt, kap_s);
+                                 "t %.9g pdf_t %.9g Lp %.9g Lm %.9g cos %.9g W %.9g wgt %.9g kappa %.3g\n",
+                                 m, k, pv.tri, p.x, p.y, p.z, nsv.x, nsv.y, nsv.z, ei, pdf, te, pdf_t, Lp, Lm, cosw, W, wgt,
+                                 kap_s);
                 V3<D> A = Ed.P(e.va), B = Ed.P(e.vb);
                 D beta = dot(lift<D>(wh), cross(A - pv.x, B - pv.x));
                 parts.emplace_back();
@@ -1374,7 +1460,8 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 sweep(C, L, beta.i, wgt, parts.back());
                 if (C.harvest) {
                     double c2 = (dot(cross(v1p, wh), cross(v1p, wh)) + dot(cross(wh, v0p), cross(wh, v0p))) * wgt * wgt;
-                    harvest.push_back({ei, pdf * c2, pdf * c2 * scales.back()});
+                    // P(edge) p(t) |c|^2: its expectation does not depend on either density
+                    harvest.push_back({ei, pdf * pdf_t * c2, pdf * pdf_t * c2 * scales.back()});
                 }
             }
         }
@@ -1477,6 +1564,28 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
 extern "C" {
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox(ctr, key, out); }
+
+int orc_edge_t_cosine(const double p[3], const double n[3], const double v0[3], const double v1[3], int32_t count,
+                      const double* u, double* t, double* pdf_t) {
+    V3d P{p[0], p[1], p[2]}, N{n[0], n[1], n[2]}, A{v0[0], v0[1], v0[2]}, B{v1[0], v1[1], v1[2]};
+    double T = cosine_arc_integral(P, N, A, B);
+    for (int i = 0; i < count; ++i) {
+        double te = -1;
+        if (!cosine_edge_t(P, N, A, B, u[i], te, nullptr)) {
+            t[i] = -1;
+            pdf_t[i] = 0;
+            continue;
+        }
+        t[i] = te;
+        pdf_t[i] = cosine_edge_pdf(P, N, A, B, te, T);
+    }
+    return ORC_OK;
+}
+
+double orc_edge_t_cosine_pdf(const double p[3], const double n[3], const double v0[3], const double v1[3], double t) {
+    V3d P{p[0], p[1], p[2]}, N{n[0], n[1], n[2]}, A{v0[0], v0[1], v0[2]}, B{v1[0], v1[1], v1[2]};
+    return cosine_edge_pdf(P, N, A, B, t, cosine_arc_integral(P, N, A, B));
+}
 
 void orc_tie_reasons(int64_t out[16], int32_t reset) {
     for (int i = 0; i < 16; ++i) {

@@ -76,6 +76,10 @@ typedef struct {
      * 4-6 shading normal x/y/z (facing the ray), 7 albedo. Gradients: interior
      * term of that value and the primary boundary term (no secondary term). */
     int32_t aov;
+    /* Point on a secondary edge: 0 = uniform in the edge parameter t, 1 = in
+     * proportion to the clamped cosine with the shading normal in the
+     * arc-length measure of its direction (closed-form inverse). */
+    int32_t edge_t_mode;
 } orc_options;
 
 typedef struct {
@@ -128,6 +132,13 @@ int  orc_edge_tree_pdf_of(const orc_scene* s, const orc_camera* c, const double 
 int  orc_edge_tree_sample(const orc_scene* s, const orc_camera* c, const double p[3],
                           const double n[3], int32_t count, const double* u,
                           int32_t* edge, double* pdf);
+
+/* The clamped-cosine edge-point sampler for one shading point (p, n) and edge
+ * (v0, v1): t[i] and its density pdf_t[i] for each uniform u[i] (t = -1,
+ * pdf_t = 0 when there is no sample), and the density at a given t. */
+int    orc_edge_t_cosine(const double p[3], const double n[3], const double v0[3], const double v1[3], int32_t count,
+                         const double* u, double* t, double* pdf_t);
+double orc_edge_t_cosine_pdf(const double p[3], const double n[3], const double v0[3], const double v1[3], double t);
 
 /* Secondary boundary factor in both measures for one edge point (for the
  * identity test between the thesis's area form and the direction form).

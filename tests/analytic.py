@@ -145,6 +145,58 @@ def two_triangle_image(verts, emission, background, cam9, fov, W, H, window=None
     return img
 
 
+def near_clip(poly3d, cam9, near):
+    """Part of a planar 3D polygon at camera-space depth >= near
+    (Sutherland-Hodgman against the near plane)."""
+    c, f, _, _ = camera_frame(cam9[0:3], cam9[3:6], cam9[6:9])
+    pts = [np.asarray(p, np.float64) for p in poly3d]
+    out = []
+    for i in range(len(pts)):
+        p, q = pts[i], pts[(i + 1) % len(pts)]
+        dp, dq = (p - c) @ f - near, (q - c) @ f - near
+        if dp >= 0:
+            out.append(p)
+        if (dp >= 0) != (dq >= 0):
+            out.append(p + (q - p) * (dp / (dp - dq)))
+    return out
+
+
+def near_clipped_two_triangle_image(verts, emission, background, cam9, fov, W, H, near, window=None):
+    """Exact box-filtered image of two non-intersecting emissive triangles
+    (constant two-sided emission) when geometry nearer than `near` (camera-
+    space depth) is invisible: each triangle is clipped against the near plane
+    in 3D, then its visible polygon is projected. The clipped polygon's new
+    side lies on the near plane and must project outside the window (it is not
+    a mesh edge)."""
+    verts = np.asarray(verts, np.float64).reshape(2, 3, 3)
+    x0, y0, x1, y1 = window if window is not None else (0, 0, W, H)
+    polys3 = [near_clip(verts[i], cam9, near) for i in range(2)]
+    s = [ccw([tuple(p) for p in project(np.array(polys3[i]), cam9, fov, W, H)]) if len(polys3[i]) >= 3 else []
+         for i in range(2)]
+    inter = clip_convex(s[0], s[1]) if s[0] and s[1] else []
+    front = 0
+    if len(inter) >= 3:
+        cx = sum(p[0] for p in inter) / len(inter)
+        cy = sum(p[1] for p in inter) / len(inter)
+        o, d = screen_ray(np.array([cx]), np.array([cy]), cam9, fov, W, H)
+        depth = []
+        for i in range(2):
+            a, b, c = verts[i]
+            n = np.cross(b - a, c - a)
+            depth.append(((a - o) @ n) / (d[0] @ n))
+        front = 0 if depth[0] < depth[1] else 1
+    back = 1 - front
+    img = np.full((y1 - y0, x1 - x0), float(background))
+    for py in range(y0, y1):
+        for px in range(x0, x1):
+            af = box_clip_area(s[front], px, py, px + 1, py + 1) if s[front] else 0.0
+            ab = box_clip_area(s[back], px, py, px + 1, py + 1) if s[back] else 0.0
+            afb = box_clip_area(inter, px, py, px + 1, py + 1) if len(inter) >= 3 else 0.0
+            img[py - y0, px - x0] = (background * (1 - af - ab + afb) + emission[front] * af
+                                     + emission[back] * (ab - afb))
+    return img
+
+
 # ---------------------------------------------------------------------------
 # Lambert: irradiance from a uniform planar polygon
 # ---------------------------------------------------------------------------
