@@ -169,11 +169,11 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
 
 TIE_REASONS = ["near_miss_in_front", "equal_t_hits", "hit_near_edge", "hit_near_tmin", "grazing_hit",
                "shadow_near_edge", "shadow_near_ends", "cdf_tie", "inside_box_tie", "horizon_tie",
-               "vsphere_tie", "branch_tie", "ill_conditioned_edge", "pixel_boundary", "silhouette_sign", "mixture_component"]
+               "vsphere_tie", "branch_tie", "ill_conditioned_edge", "pixel_boundary", "silhouette_sign", "mixture_component", "grazing_departure"]
 
 
 def tie_reasons(reset=True):
-    out = np.zeros(16, np.int64)
+    out = np.zeros(20, np.int64)
     lib().orc_tie_reasons(_vp(out), int(reset))
     return {k: int(v) for k, v in zip(TIE_REASONS, out) if v}
 

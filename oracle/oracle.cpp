@@ -39,15 +39,16 @@ const double kPi = 3.14159265358979323846;
 // is flagged when one of its discrete decisions lies this close to a tie, so
 // that an FP32 implementation may legitimately decide the other way.
 // ---------------------------------------------------------------------------
-const double kTieWorld = 5e-7;    // ray-to-triangle-edge distance, relative to the scene diagonal
+const double kTieWorld = 2.5e-7;  // ray-to-triangle-edge distance, relative to the scene diagonal
 const double kTieT = 1e-6;        // relative distance between hit distances
 const double kTieCos = 1e-5;      // |cos| of grazing hits
 const double kTieU = 1e-5;        // uniform vs. branch probability
-const double kTieCdf = 2e-6;      // uniform vs. FP64 CDF built from FP32 lengths/areas
+const double kTieCdf = 5e-7;      // uniform vs. FP64 CDF built from FP32 lengths/areas
 const double kTieSign = 1e-5;     // relative plane-side tests
 const double kTiePx = 1e-3;       // edge point vs. pixel boundary (pixels)
 const double kTieCond = 1e-3;     // sin(angle(v0', v1')) of secondary edges
 const double kTieBox = 1e-6;      // relative point-in-box / sphere tests
+const double kTieDepart = 1e-6;   // FP32 error of a surface point, relative to max(1, |x|) (rays leaving a surface)
 
 // Constants of the estimator (shared by specification with the GPU path).
 const double kEpsPx = 1e-3;       // primary: offset of the two sides, pixels
@@ -326,7 +327,7 @@ int prepare(const orc_scene* d, Scn& s) {
 // Ray casting with near-tie detection
 // ---------------------------------------------------------------------------
 // Per-reason counters of near-tie flags (diagnostics for the tests).
-int64_t g_reason[16];
+int64_t g_reason[20];
 #define TIE(U, r) do { (U).flag = true; __atomic_add_fetch(&g_reason[r], 1, __ATOMIC_RELAXED); } while (0)
 
 struct Unit {
@@ -398,6 +399,14 @@ void for_candidates(const Scn& s, const V3d& o, const V3d& d, double tmin, doubl
 
 struct Hit { int tri; double t, u, v; };
 
+// Near-edge threshold of triangle f for a ray along d, in barycentric units:
+// an FP32 ray's crossing of the triangle's plane is off by its across-ray
+// error divided by the incidence cosine, so grazing rays get a wider margin.
+double edge_tie(const Scn& s, int f, const V3d& d) {
+    double c = std::fabs(dot(normalize(s.face_n(f)), normalize(d)));
+    return s.tie_bary[f] / std::max(c, kTieCos);
+}
+
 // Closest hit in (tmin, tmax); ties in t go to the smaller triangle id.
 Hit closest(const Scn& s, const V3d& o, const V3d& d, double tmin, double tmax, Unit& U) {
     U.rays++;
@@ -408,7 +417,7 @@ Hit closest(const Scn& s, const V3d& o, const V3d& d, double tmin, double tmax, 
         TriHit h = tri_test(s, f, o, d, tmin, tmax);
         if (!h.valid) return;
         if (h.ok && (h.t < best.t || (h.t == best.t && f < best.tri))) best = {f, h.t, h.u, h.v};
-        bool near_edge = std::fabs(h.m) < s.tie_bary[f];
+        bool near_edge = std::fabs(h.m) < edge_tie(s, f, d);
         bool in_range = h.t > tmin * (1 - kTieT) - 1e-300 && h.t < tmax * (1 + kTieT);
         if ((near_edge && in_range) || h.ok) nears.push_back({f, h.t, h.ok});
     });
@@ -422,7 +431,7 @@ Hit closest(const Scn& s, const V3d& o, const V3d& d, double tmin, double tmax, 
     }
     if (best.tri >= 0) {
         double m = std::min(std::min(best.u, best.v), 1 - best.u - best.v);
-        if (m < s.tie_bary[best.tri]) TIE(U, 2);
+        if (m < edge_tie(s, best.tri, d)) TIE(U, 2);
         if (std::fabs(best.t - tmin) <= kTieT * std::max(best.t, tmin)) TIE(U, 3);
         V3d n = normalize(s.face_n(best.tri));
         if (std::fabs(dot(n, normalize(d))) < kTieCos) TIE(U, 4);
@@ -439,8 +448,9 @@ bool occluded(const Scn& s, const V3d& o, const V3d& d, double tmin, double tmax
         if (!h.valid) return;
         if (h.ok) any = true;
         bool in_range = h.t > tmin * (1 - kTieT) && h.t < tmax * (1 + kTieT);
-        if (in_range && std::fabs(h.m) < s.tie_bary[f]) TIE(U, 5);
-        if (h.ok || std::fabs(h.m) < s.tie_bary[f]) {
+        double tie = edge_tie(s, f, d);
+        if (in_range && std::fabs(h.m) < tie) TIE(U, 5);
+        if (h.ok || std::fabs(h.m) < tie) {
             if (std::fabs(h.t - tmin) <= kTieT * std::max(h.t, tmin) || std::fabs(h.t - tmax) <= kTieT * tmax)
                 TIE(U, 6);
         }
@@ -1058,8 +1068,17 @@ double emitted(const Scn& s, int tri, bool front) {
 // square-root warp, one shadow ray. The sampled direction is held fixed and
 // its solid-angle pdf is a constant under differentiation, so only the
 // albedo and the shading cosine carry derivatives.
+// A ray leaving a point x of triangle `tri` along w rises t |n . w| off the
+// triangle's plane at distance t. An FP32 implementation places x within a
+// few ulps of that plane, so when the rise at t_min is within that error it
+// may hit its own triangle or miss it: a near tie.
+void departure_tie(const Scn& s, int tri, const V3d& x, const V3d& w, Unit& U) {
+    double c = std::fabs(dot(normalize(s.face_n(tri)), normalize(w)));
+    if (c * s.tmin < kTieDepart * std::max(1.0, length(x))) TIE(U, 16);
+}
+
 template <class S> S nee(const Env<S>& E, Unit& U, const Stream& rs, int blk, const V3<S>& x, const V3<S>& ns, const S& rho,
-                         double* log) {
+                         double* log, int tri) {
     const Scn& s = *E.s;
     if (s.lights.empty()) return cst<S>(0);
     if (log && U.dir_mode == 2) {
@@ -1087,6 +1106,7 @@ template <class S> S nee(const Env<S>& E, Unit& U, const Stream& rs, int blk, co
     if (s.two_sided) cy = std::fabs(cy);
     S cp = dot(ns, lift<S>(wh));
     if (val(cp) <= 0 || cy <= 0) return cst<S>(0);
+    departure_tie(s, tri, xv, wh, U);
     if (occluded(s, xv, wh, s.tmin, r * (1 - kShadowEnd), U)) return cst<S>(0);
     double k = s.emi[lt] * cy / r2 * s.atot / kPi;
     if (log) { log[0] = wh.x; log[1] = wh.y; log[2] = wh.z; log[3] = k; log[4] = 1; }
@@ -1140,7 +1160,7 @@ S radiance_impl(const Env<S>& E, Unit& U, const Stream& rs, int base, const V3<S
         }
         if (log) log->push_back(PathVtx<S>{x, ns, rho, beta, tri, dxv, kap});
         double* dl = (log && U.dir_mode && k <= 6) ? U.dir + 10 * (k - 1) : nullptr;
-        L = L + beta * nee(E, U, rs, base + 2 * k - 1, x, ns, rho, dl);
+        L = L + beta * nee(E, U, rs, base + 2 * k - 1, x, ns, rho, dl, tri);
         if (k == budget) break;
         double u[4];
         rs.block(base + 2 * k, u);
@@ -1150,6 +1170,7 @@ S radiance_impl(const Env<S>& E, Unit& U, const Stream& rs, int base, const V3<S
         if (dl && U.dir_mode == 2) { w = V3d{dl[5], dl[6], dl[7]}; cv = dl[8]; }
         if (dl && U.dir_mode == 1) { dl[5] = w.x; dl[6] = w.y; dl[7] = w.z; dl[8] = cv; }
         if (cv <= 0) break;
+        departure_tie(s, tri, valv(x), w, U);
         Hit h2 = closest(s, valv(x), w, s.tmin, 1e300, U);
         if (h2.tri < 0) break;
         // Continuation weight f*cos/pdf with the pdf held constant.
@@ -1434,6 +1455,8 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 cp.dx = cm.dx = pv.dx;
                 cp.dw = cm.dw = 8 + pv.dx / wl;
                 cp.kmax = cm.kmax = pv.kappa;
+                departure_tie(s, pv.tri, p, wp, U);
+                departure_tie(s, pv.tri, p, wm, U);
                 // the same limit rule as for primary edges
                 bool same = closest(s, p, wp, s.tmin, 1e300, U).tri == closest(s, p, wm, s.tmin, 1e300, U).tri;
                 double Lp = same ? 0.0 : radiance_impl<double>(Ev, U, rk, kSideBlockBase, p, wp, s.tmin, false, rem, nullptr, &cp);
@@ -1587,8 +1610,8 @@ double orc_edge_t_cosine_pdf(const double p[3], const double n[3], const double 
     return cosine_edge_pdf(P, N, A, B, t, cosine_arc_integral(P, N, A, B));
 }
 
-void orc_tie_reasons(int64_t out[16], int32_t reset) {
-    for (int i = 0; i < 16; ++i) {
+void orc_tie_reasons(int64_t out[20], int32_t reset) {
+    for (int i = 0; i < 20; ++i) {
         out[i] = g_reason[i];
         if (reset) g_reason[i] = 0;
     }

@@ -109,7 +109,7 @@ int  orc_render(const orc_scene* s, const orc_camera* c, const orc_options* o, o
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
 /* Diagnostic counters of near-tie flags by reason (see oracle.cpp). */
-void orc_tie_reasons(int64_t out[16], int32_t reset);
+void orc_tie_reasons(int64_t out[20], int32_t reset);
 
 /* Unique undirected edges: rows (va, vb, f0, f1), va < vb, f1 = -1 on a boundary. */
 int  orc_edges(const orc_scene* s, int32_t* num_edges, int32_t* rows /* [E][4] or NULL */);
