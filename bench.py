@@ -82,38 +82,71 @@ def cpu_baseline(cfg, threads):
 
 def proposal_leg(threads_note=None):
     """Learned edge proposal on the 1,000-triangle scene (direct lighting):
-    harvest per-edge boundary magnitudes over 256 seeded training views
-    (128x128, 8 spp), train the 32-64-64-1 network (600 full-batch Adam steps
-    on the GPU), then compare gradient variance x backward time of the plain
-    sampler and the 0.8/0.2 mixture on 4 held-out views (128x128, 16 spp,
-    512 seeds each: the secondary term's variance is heavy-tailed, so its
-    estimate needs many seeds), per term and for the whole gradient
-    (d_image = 1)."""
-    import torch
-
+    harvest per-edge boundary magnitudes over 332 seeded training views
+    (128x128, 16 spp: ~1.0 M (edge, view) rows), train the 32-64-64-1 network
+    (600 full-batch Adam steps on the GPU), then compare the plain sampler and
+    the 0.8/0.2 mixture on 16 held-out views at the configuration's 256x256
+    and 16 spp, 64 seeds per view and sampler: gradient variance x backward
+    time per term and for the whole gradient (d_image = 1), the learned time
+    including its per-view proposal, with bootstrap 95% intervals and a
+    per-entry Welch test of equal means."""
     from paper_1904_12228_amd import api, proposal, scenegen
 
     cfg = scenegen.config2()
     S = api.Scene(cfg.scene)
-    train = [c for c, _ in scenegen.orbit_views(1, 256)]
+    train = [c for c, _ in scenegen.orbit_views(1, 332)]
     t0 = proposal.seconds()
-    ds = proposal.harvest(S, train, 8, 1)
+    ds = proposal.harvest(S, train, 16, 1)
     t1 = proposal.seconds()
     prop = proposal.EdgeProposal(scenegen.mlp_params(0))
     loss0 = prop.loss(ds)
     prop.train(ds, 600)
     t2 = proposal.seconds()
     loss1 = prop.loss(ds)
-    base = cfg.camera
-    held = [(scenegen.Camera(base.position, base.look_at, base.up, base.fov_y_deg, 128, 128), 16)]
-    held += scenegen.orbit_views(99, 3, sizes=((128, 128),), spp=(16,))
-    res = proposal.evaluate(S, prop, held, 1, list(range(512)))
+    held = scenegen.orbit_views(99, 16, sizes=((256, 256),), spp=(16,))
+    print("proposal: trained, evaluating", file=sys.stderr, flush=True)
+    res = proposal.evaluate_protocol(S, prop, held, 1, list(range(1, 65)))
     S.close()
-    return {"workload": "1,000-triangle soup + ground + quad light, depth 1; 4 held-out views 128x128 at 16 spp, "
-                        "512 seeds per sampler; mixture 0.8 learned / 0.2 plain",
-            "metric": "gradient variance x time gain (plain / learned), higher is better",
+    return {"workload": "1,000-triangle soup + ground + quad light, depth 1; 16 held-out views 256x256 at 16 spp, "
+                        "64 seeds per view and sampler; mixture 0.8 learned / 0.2 plain",
+            "metric": "gradient variance x time gain (plain / learned), higher is better; 95% bootstrap interval",
             "train_views": len(train), "train_rows": int(ds.x.shape[0]), "harvest_s": t1 - t0, "train_s": t2 - t1,
-            "train_loss": [loss0, loss1], "per_term": res, "gain_total": res["total"]["gain"]}
+            "train_loss": [loss0, loss1], "per_term": res, "gain_total": res["total"]["gain"],
+            "gain_total_ci95": res["total"]["gain_ci95"]}
+
+
+def edge_points_leg():
+    """Points on secondary edges drawn by the clamped cosine against uniform
+    points: gradient variance x backward time of the secondary term and of the
+    whole gradient (d_image = 1), 64 seeds per sampler, on 4 views of the
+    1,000-triangle scene (256x256, 16 spp, depth 1) and on a 128x128 window of
+    the 81,936-triangle depth-3 scene (8 spp)."""
+    from paper_1904_12228_amd import api, proposal, scenegen
+
+    out = {}
+    for name, cfg, views, depth in (
+            ("config2", scenegen.config2(), None, 1),
+            ("config3_window", scenegen.config3(), None, 3)):
+        S = api.Scene(cfg.scene)
+        if name == "config2":
+            views = [(cfg.camera, 16)] + scenegen.orbit_views(77, 3, sizes=((256, 256),), spp=(16,))
+        else:
+            views = [(cfg.camera.with_window(192, 192, 320, 320), 8)]
+        res = {}
+        for term, terms in (("secondary", 4), ("total", 0)):
+            plain, cosine = [], []
+            for i, (cam, spp) in enumerate(views):
+                seeds = [s + 1000 * i for s in range(64)]
+                G, ta = proposal.gradient_samples(S, cam, spp, depth, seeds, terms=terms)
+                H, tb = proposal.gradient_samples(S, cam, spp, depth, [s + 500 for s in seeds], terms=terms, edge_t=1)
+                plain.append((G, sorted(ta)[len(ta) // 2]))
+                cosine.append((H, sorted(tb)[len(tb) // 2]))
+            res[term] = proposal.variance_time_stats(plain, cosine)
+        out[name] = res
+        S.close()
+        print(f"edge points: {name} done", file=sys.stderr, flush=True)
+    return {"metric": "gradient variance x time gain (uniform points / clamped-cosine points), 95% bootstrap "
+                      "interval", **out}
 
 
 def gbuffer_leg(S, cam, spp, d_image, reps=3):
@@ -237,6 +270,8 @@ def main():
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal variance x time leg")
     ap.add_argument("--no-inverse", action="store_true", help="skip the batched inverse-rendering leg")
     ap.add_argument("--no-gbuffer", action="store_true", help="skip the geometry-buffer leg")
+    ap.add_argument("--no-edge-points", action="store_true",
+                    help="skip the clamped-cosine vs uniform edge-point variance x time leg")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one plain device copy of 256 MiB (reference for HBM byte counters)")
@@ -345,6 +380,9 @@ def main():
     if not args.no_proposal:
         print("running the learned-proposal leg", file=sys.stderr, flush=True)
         out["proposal"] = proposal_leg()
+    if not args.no_edge_points:
+        print("running the edge-point sampling leg", file=sys.stderr, flush=True)
+        out["edge_points"] = edge_points_leg()
     if not args.no_inverse:
         print("running the batched inverse-rendering leg", file=sys.stderr, flush=True)
         out["inverse_rendering"] = inverse_leg()

@@ -124,6 +124,13 @@ typedef struct {
      * Not combined with edge_pdf, edge_mix > 0 or edge_stats
      * (DR_ERROR_INVALID_VALUE); batches take 0 only. */
     int32_t  aov;
+    /* Point on each secondary edge sample (drRenderBackward only; Ch. 5,
+     * Importance sampling on an edge): 0 = uniform in the edge parameter t;
+     * 1 = in proportion to the clamped cosine with the shading normal, in the
+     * arc-length measure of the direction toward the point (closed-form
+     * inverse; the Lambertian case of sampling the shading lobe along the
+     * edge), weighted by its density. Other values: DR_ERROR_INVALID_VALUE. */
+    int32_t  edge_t_mode;
 } drRenderOptions;
 
 /* Creates a scene: validates sizes and indices (host copy of the topology),
@@ -144,7 +151,8 @@ drStatus drSceneUpdateVertices(drScene scene, const float* vertices, hipStream_t
 /* Replaces all triangle albedos ([T] device, in [0, 1]) for material
  * fitting (Ch. 5, Results: inverse rendering of material parameters);
  * refreshes the edge kinds, which depend on the albedos of an edge's two
- * faces. The values are not checked. */
+ * faces. Kernel launches only (no synchronisation). The values are not
+ * checked. */
 drStatus drSceneUpdateAlbedo(drScene scene, const float* albedo, hipStream_t stream);
 
 /* Host query of the scene's sizes. */
@@ -180,8 +188,9 @@ typedef struct drBatch_t* drBatch;
 drStatus drSceneRefit(drScene scene, const float* vertices, hipStream_t stream);
 
 /* Creates a batch of n views of `scene` (which must outlive it): cameras[n]
- * and options[n] (host arrays, copied; all views share max_depth; unit_mask,
- * edge_pdf and edge_stats must be NULL and edge_mix 0), images[n] and
+ * and options[n] (host arrays, copied; all views share max_depth; edge_pdf
+ * and edge_stats must be NULL and edge_mix 0; a view's unit_mask, if given,
+ * is read by every later pass and must stay alive with the batch), images[n] and
  * d_images[n] (host arrays of device pointers, each [H][W] of its view's
  * window, owned by the caller and used by every later call). Builds each
  * view's primary edge table and edge hierarchy; synchronises `stream`. */
@@ -190,8 +199,22 @@ drStatus drBatchCreate(drBatch* out, drScene scene, int32_t n, const drCamera* c
                        hipStream_t stream);
 
 /* Per-view tables from the scene's current vertices (after drSceneRefit),
- * keeping each hierarchy's topology. Capturable. */
+ * keeping each hierarchy's topology. Capturable. Which edges are
+ * discontinuities, and which hierarchy holds them, can change when vertices
+ * move (coplanar faces folding into a crease, a smooth edge becoming a
+ * silhouette from the camera); the refit then raises a device flag of the
+ * batch, which drBatchCheckHierarchy reads. */
 drStatus drBatchRefit(drBatch batch, hipStream_t stream);
+
+/* Reads the flag drBatchRefit raises (synchronises `stream`). If it is set,
+ * rebuilds every view's primary edge table and edge hierarchies from the
+ * scene's current vertices, clears the flag and sets *rebuilt = 1, else
+ * *rebuilt = 0. Call it after drBatchRefit and before the next
+ * drBatchBackward: a backward pass over a flagged batch misses boundary
+ * terms. Not capturable; a HIP graph captured before a rebuild must be
+ * captured again (its refit launches carry the old hierarchy sizes). Device
+ * addresses held by the batch do not change. */
+drStatus drBatchCheckHierarchy(drBatch batch, int32_t* rebuilt, hipStream_t stream);
 
 /* Adds 1 to every view's Philox key (new random numbers for the next
  * forward/backward pair). Capturable. */

@@ -22,7 +22,8 @@ EXPORTS = ["drSceneCreate", "drSceneUpdateVertices", "drSceneUpdateAlbedo", "drS
            "drRenderBackward", "drAdamStep", "drSetProfiling", "drGetProfile", "drGetLastDeviceError", "drSceneDestroy",
            "drGetErrorString", "drEdgeFeatures", "drMlpForward", "drMlpSoftmaxXent", "drMlpBackward",
            "drSceneRefit", "drBatchCreate", "drBatchRefit", "drBatchAdvanceSeed", "drBatchForward", "drBatchBackward",
-           "drBatchSetLaunch", "drBatchDestroy", "drAdamStepCounted", "drMlpSoftmaxXentNoAlloc"]
+           "drBatchSetLaunch", "drBatchDestroy", "drAdamStepCounted", "drMlpSoftmaxXentNoAlloc",
+           "drBatchCheckHierarchy"]
 
 MLP_PARAMS = 6337
 EDGE_FEATURES = 32
@@ -45,7 +46,7 @@ class RenderOptions(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("view_id", C.c_uint32), ("terms", C.c_uint32), ("unit_mask", C.c_void_p),
                 ("edge_pdf", C.c_void_p), ("edge_mix", C.c_float), ("edge_mix_terms", C.c_uint32),
-                ("edge_stats", C.c_void_p), ("aov", C.c_int32)]
+                ("edge_stats", C.c_void_p), ("aov", C.c_int32), ("edge_t_mode", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -94,6 +95,7 @@ def load():
         "drBatchCreate": [C.POINTER(vp), vp, i32, C.POINTER(Camera), C.POINTER(RenderOptions), C.POINTER(vp),
                           C.POINTER(vp), vp],
         "drBatchRefit": [vp, vp],
+        "drBatchCheckHierarchy": [vp, C.POINTER(i32), vp],
         "drBatchAdvanceSeed": [vp, vp],
         "drBatchForward": [vp, vp],
         "drBatchBackward": [vp, vp, vp, vp, vp],

@@ -40,9 +40,10 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 def options_struct(spp, max_depth, seed=0, view_id=0, terms=0, unit_mask=None, edge_pdf=None, edge_mix=0.0,
-                   edge_mix_terms=0, edge_stats=None, aov=0) -> _lib.RenderOptions:
+                   edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0) -> _lib.RenderOptions:
     return _lib.RenderOptions(int(spp), int(max_depth), int(seed), int(view_id), int(terms), _ptr(unit_mask),
-                              _ptr(edge_pdf), float(edge_mix), int(edge_mix_terms), _ptr(edge_stats), int(aov))
+                              _ptr(edge_pdf), float(edge_mix), int(edge_mix_terms), _ptr(edge_stats), int(aov),
+                              int(edge_t))
 
 
 # geometry-buffer channels of drRenderOptions.aov
@@ -79,6 +80,14 @@ class Scene:
         self.vertices = v
         _lib.check(_lib.load().drSceneUpdateVertices(self._h, _ptr(v), _stream()), "drSceneUpdateVertices")
 
+    def refit_vertices(self, vertices):
+        """Vertex update over the existing BVH topology (drSceneRefit): kernel
+        launches only, no host synchronisation and no host BVH build."""
+        v = _dev(vertices, torch.float32, self.device).contiguous()
+        assert v.shape == (self.num_vertices, 3)
+        self.vertices = v
+        _lib.check(_lib.load().drSceneRefit(self._h, _ptr(v), _stream()), "drSceneRefit")
+
     def update_albedo(self, albedo):
         a = _dev(albedo, torch.float32, self.device)
         assert a.shape == (self.num_triangles,)
@@ -99,12 +108,13 @@ class Scene:
 
     def render_backward(self, cam, spp, max_depth, d_image, seed=0, view_id=0, terms=0, unit_mask=None,
                         want=("vertices", "albedo", "camera"), outs=None, edge_pdf=None, edge_mix=0.0,
-                        edge_mix_terms=0, edge_stats=None, aov=0):
+                        edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0):
         """Gradients w.r.t. vertices [V,3], albedo [T] and camera [9]. With
         edge_pdf ([E] device distribution) and edge_mix > 0 the edge samples
         are drawn from the proposal mixture; edge_stats ([E] float32 device
         tensor) receives the harvest statistic. aov selects the image being
-        differentiated, as in render."""
+        differentiated, as in render. edge_t = 1 draws the point on each
+        secondary edge by the clamped cosine instead of uniformly."""
         d_image = _dev(d_image, torch.float32, self.device)
         x0, y0, x1, y1 = cam.win()
         assert d_image.numel() == (7 if aov == 8 else 1) * (y1 - y0) * (x1 - x0), "d_image size"
@@ -120,7 +130,7 @@ class Scene:
         if edge_stats is not None:
             assert edge_stats.dtype == torch.float32 and edge_stats.is_contiguous() and edge_stats.numel() == self.num_edges
         o = options_struct(spp, max_depth, seed, view_id, terms, unit_mask, edge_pdf, edge_mix, edge_mix_terms,
-                           edge_stats, aov)
+                           edge_stats, aov, edge_t)
         _lib.check(_lib.load().drRenderBackward(self._h, C.byref(c), C.byref(o), _ptr(d_image), _ptr(dv), _ptr(da),
                                                 _ptr(dc), _stream()), "drRenderBackward")
         return dv, da, dc

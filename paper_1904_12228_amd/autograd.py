@@ -18,28 +18,35 @@ from .scenegen import Camera
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, vertices, camera9, scene: api.Scene, cam: Camera, spp: int, depth: int, seed: int, view_id: int):
-        scene.update_vertices(vertices)
+    def forward(ctx, vertices, camera9, albedo, scene: api.Scene, cam: Camera, spp: int, depth: int, seed: int,
+                view_id: int, unit_mask):
+        # the BVH topology is kept (refit): no host build inside an optimisation loop
+        scene.refit_vertices(vertices.detach())
+        if albedo is not None:
+            scene.update_albedo(albedo.detach())
         c = Camera.from_params9(camera9.detach().cpu().numpy(), cam)
-        img = scene.render(c, spp, depth, seed=seed, view_id=view_id)
-        ctx.args = (scene, c, spp, depth, seed, view_id)
+        img = scene.render(c, spp, depth, seed=seed, view_id=view_id, unit_mask=unit_mask)
+        ctx.args = (scene, c, spp, depth, seed, view_id, unit_mask)
         ctx.cam_device = camera9.device
+        ctx.has_albedo = albedo is not None
         return img
 
     @staticmethod
     def backward(ctx, d_img):
-        scene, c, spp, depth, seed, view_id = ctx.args
-        dv, _, dc = scene.render_backward(c, spp, depth, d_img.contiguous(), seed=seed, view_id=view_id,
-                                          want=("vertices", "camera"))
-        return dv, dc.to(ctx.cam_device), None, None, None, None, None, None
+        scene, c, spp, depth, seed, view_id, unit_mask = ctx.args
+        want = ("vertices", "camera", "albedo") if ctx.has_albedo else ("vertices", "camera")
+        dv, da, dc = scene.render_backward(c, spp, depth, d_img.contiguous(), seed=seed, view_id=view_id,
+                                           unit_mask=unit_mask, want=want)
+        return dv, dc.to(ctx.cam_device), da, None, None, None, None, None, None, None
 
 
 def render(scene: api.Scene, vertices: torch.Tensor, camera9: torch.Tensor, cam: Camera, spp: int, depth: int,
-           seed: int = 0, view_id: int = 0) -> torch.Tensor:
+           seed: int = 0, view_id: int = 0, albedo: torch.Tensor | None = None, unit_mask=None) -> torch.Tensor:
     """Differentiable render: image of `scene` with the given vertex positions
-    ([V,3] on the scene's device) and camera (9 numbers: position, look_at,
-    up; fov and image size from `cam`)."""
-    return _RenderFn.apply(vertices, camera9, scene, cam, spp, depth, seed, view_id)
+    ([V,3] on the scene's device), camera (9 numbers: position, look_at, up;
+    fov and image size from `cam`) and, optionally, per-triangle albedo ([T];
+    then its gradient is returned too). unit_mask as in Scene.render."""
+    return _RenderFn.apply(vertices, camera9, albedo, scene, cam, spp, depth, seed, view_id, unit_mask)
 
 
 ALL_CHANNELS = (1, 2, 3, 4, 5, 6, 7)

@@ -40,7 +40,7 @@ class Batch:
     """Views [(Camera, spp)] of one scene, all with path depth `depth`.
     images[v] / d_images[v] are [H, W] device tensors owned here."""
 
-    def __init__(self, scene: api.Scene, views, depth: int, seed: int = 0):
+    def __init__(self, scene: api.Scene, views, depth: int, seed: int = 0, unit_masks=None):
         self.scene = scene
         self.views = list(views)
         n = len(self.views)
@@ -54,6 +54,9 @@ class Batch:
             self.d_images.append(torch.zeros((y1 - y0, x1 - x0), dtype=torch.float32, device=dev))
             cams[i] = api.camera_struct(cam)
             opts[i] = api.options_struct(spp, depth, seed, i)
+            if unit_masks is not None and unit_masks[i] is not None:
+                opts[i].unit_mask = unit_masks[i].data_ptr()
+        self.unit_masks = unit_masks      # read by every pass: kept alive with the batch
         ip = (C.c_void_p * n)(*[t.data_ptr() for t in self.images])
         dp = (C.c_void_p * n)(*[t.data_ptr() for t in self.d_images])
         h = C.c_void_p()
@@ -69,6 +72,14 @@ class Batch:
 
     def refit(self):
         _lib.check(_lib.load().drBatchRefit(self._h, _s()), "drBatchRefit")
+
+    def check_hierarchy(self) -> bool:
+        """Rebuilds the views' edge hierarchies if the last refit moved an
+        edge into a discontinuity class its kept hierarchy cannot represent
+        (synchronises); returns whether it rebuilt."""
+        flag = C.c_int32(0)
+        _lib.check(_lib.load().drBatchCheckHierarchy(self._h, C.byref(flag), _s()), "drBatchCheckHierarchy")
+        return bool(flag.value)
 
     def advance_seed(self):
         _lib.check(_lib.load().drBatchAdvanceSeed(self._h, _s()), "drBatchAdvanceSeed")
@@ -107,6 +118,7 @@ class BatchRenderFn(torch.autograd.Function):
     def forward(ctx, vertices, batch: Batch):
         scene_refit(batch.scene, vertices.detach().contiguous())
         batch.refit()
+        batch.check_hierarchy()
         batch.advance_seed()
         batch.forward()
         ctx.batch = batch
@@ -132,9 +144,12 @@ def render_views(vertices: torch.Tensor, batch: Batch):
 class InverseRendering:
     """Adam on vertex positions to match target images of every view:
     loss = sum over views of mean over pixels (I_v - T_v)^2. `mask` [V] (1 =
-    optimised). One step is refit -> per-view refit -> new seed -> forward ->
-    loss gradient -> backward -> Adam, all on one stream; `capture()` records
-    it once as a HIP graph for replay."""
+    optimised). One step is new seed -> forward -> loss gradient -> backward
+    -> Adam -> refit of the scene and the views to the new vertices, all on
+    one stream; `capture()` records it once as a HIP graph for replay. After
+    every step the host reads the refit's hierarchy flag and, when an edge
+    changed discontinuity class, rebuilds the hierarchies (and captures the
+    graph again) before the next step renders."""
 
     def __init__(self, batch: Batch, vertices0: torch.Tensor, targets, mask: torch.Tensor, lr=2e-3):
         dev = batch.scene.device
@@ -149,11 +164,20 @@ class InverseRendering:
         self.lr = float(lr)
         self.scale = [2.0 / t.numel() for t in self.targets]
         self.graph = None
+        self.rebuilds = 0
+        scene_refit(batch.scene, self.v)
+        batch.refit()
+        self._check()
+
+    def _check(self):
+        if self.b.check_hierarchy():
+            self.rebuilds += 1
+            if self.graph is not None:
+                self.graph = None
+                self._capture_only()
 
     def _step(self):
         b = self.b
-        scene_refit(b.scene, self.v)
-        b.refit()
         b.advance_seed()
         b.forward()
         for img, tgt, dimg, sc in zip(b.images, self.targets, b.d_images, self.scale):
@@ -164,12 +188,21 @@ class InverseRendering:
         _lib.check(_lib.load().drAdamStepCounted(_p(self.v), _p(self.grad), _p(self.m), _p(self.s), self.v.numel(),
                                                  self.lr, 0.9, 0.999, 1e-8, _p(self.step_count), _s()),
                    "drAdamStepCounted")
+        scene_refit(b.scene, self.v)
+        b.refit()
 
     def step(self):
         if self.graph is not None:
             self.graph.replay()
         else:
             self._step()
+        self._check()
+
+    def _capture_only(self):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._step()
+        self.graph = g
 
     def capture(self):
         """Record one step as a HIP graph (after one eager warm-up step on the
@@ -179,11 +212,9 @@ class InverseRendering:
         with torch.cuda.stream(side):
             self._step()
         torch.cuda.current_stream().wait_stream(side)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self._step()
-        self.graph = g
-        return g
+        self._check()
+        self._capture_only()
+        return self.graph
 
     def loss(self) -> float:
         return float(sum(((img - t) ** 2).mean() for img, t in zip(self.b.images, self.targets)))

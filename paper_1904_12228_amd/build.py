@@ -10,7 +10,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdiffrt.so")
-SOURCES = ["dr_api.hip", "dr_build.hip", "dr_render.hip", "dr_optim.hip", "dr_mlp.hip", "dr_batch.hip"]
+SOURCES = ["dr_api.hip", "dr_build.hip", "dr_render.hip", "dr_render_fwd.hip", "dr_render_prim.hip",
+           "dr_render_d1.hip", "dr_render_d3.hip", "dr_render_d3x.hip", "dr_render_d6.hip", "dr_render_d6x.hip",
+           "dr_render_batch.hip", "dr_render_batch_d1.hip", "dr_render_batch_d3.hip", "dr_render_batch_d6.hip",
+           "dr_optim.hip", "dr_mlp.hip", "dr_batch.hip"]
 ARCH = os.environ.get("DIFFRT_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -36,7 +39,7 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with concurrent.futures.ThreadPoolExecutor(len(SOURCES)) as ex:
+    with concurrent.futures.ThreadPoolExecutor(min(len(SOURCES), os.cpu_count() or 8)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]

@@ -49,7 +49,7 @@ static void release_all(drScene_t* s) {
                    &s->ecode_s, &s->elist_s, &s->ekeys, &s->eparent, &s->ecounter, &s->etree, &s->ebounds, &s->edepth,
                    &s->ck_tri, &s->ck_x, &s->ck_vis, &s->camacc};
     for (Buf* b : bufs) b->release();
-    for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount, &s->svtri, &s->svx}) b->release();
+    for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount, &s->svtri, &s->svx, &s->pq, &s->pcount}) b->release();
     s->counters.release();
     for (auto& e : s->evs) {
         (void)hipEventDestroy(e.a);
@@ -73,7 +73,7 @@ bool valid_options(const drRenderOptions* o) {
     return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0 &&
            o->edge_mix >= 0.0f && o->edge_mix < 1.0f &&
            (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) == 0 && o->aov >= 0 && o->aov <= 8 &&
-           (o->aov == 0 || (o->edge_mix == 0.0f && !o->edge_stats));
+           (o->aov == 0 || (o->edge_mix == 0.0f && !o->edge_stats)) && (o->edge_t_mode == 0 || o->edge_t_mode == 1);
 }
 
 ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {
@@ -160,6 +160,7 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     s->two_sided = d->emission_two_sided ? 1 : 0;
     s->background = d->background;
     if (const char* e = std::getenv("DIFFRT_SPLIT_BACKWARD")) s->split_backward = std::atoi(e) != 0;
+    if (const char* e = std::getenv("DIFFRT_SPLIT_PRIMARY")) s->split_primary = std::atoi(e) != 0;
     // triangle BVH topology: binned SAH on the host (default) or Morton-code LBVH on the device
     if (const char* e = std::getenv("DIFFRT_BVH")) s->sah_bvh = std::strcmp(e, "lbvh") != 0;
     s->hI = I;
@@ -225,12 +226,13 @@ drStatus drSceneUpdateVertices(drScene s, const float* vertices, hipStream_t st)
 drStatus drSceneUpdateAlbedo(drScene s, const float* albedo, hipStream_t st) {
     if (!s || !albedo) return DR_ERROR_INVALID_VALUE;
     API_CHECK(hipMemcpyAsync(s->alb.p, albedo, sizeof(float) * s->T, hipMemcpyDeviceToDevice, st));
-    // edge kinds depend on the albedos of the two faces; paths stop at black surfaces
+    // edge kinds depend on the albedos of the two faces (paths read the
+    // albedos at every hit; nothing else depends on them)
     s->version++;
     s->tree_valid = false;
     s->ck_valid = false;
     s->last_stream = st;
-    return build_scene_static(s, st);
+    return refresh_edge_kinds(s, st);
 }
 
 drStatus drSceneGetInfo(drScene s, int32_t* nv, int32_t* nt, int32_t* ne) {

@@ -24,6 +24,7 @@ struct RenderArgs {
     int gshards;
     long gstride;
     int aov;           // 0: radiance; 1..7: geometry-buffer channel (the _aov kernels)
+    int edge_t;        // point on a secondary edge: 0 uniform in t, 1 by the clamped cosine
 };
 
 // Learned-proposal mixture and harvest (the <.., MIX = true> kernel variants).

@@ -23,16 +23,65 @@ struct drBatch_t {
     size_t scan_bytes = 0;
     Buf ck_tri, ck_x, ck_vis, pe, pcdf, eleaf, elist, eparent, camacc, views, boff, queue, plen, counter, depth_scr,
         scan_tmp, dv_scr;   // dv_scr: gradient copies [shards][3V + T]
+    Buf cls, stale;         // [n][E] edge classes the hierarchies were built with; int flag set by refits
     std::vector<Buf> etree, enpar;
+    std::vector<ViewKey> keys;
+    std::vector<BatchView> hv;   // host copy of the views' arguments
 
     void release() {
         for (Buf* b : {&ck_tri, &ck_x, &ck_vis, &pe, &pcdf, &eleaf, &elist, &eparent, &camacc, &views, &boff, &queue, &plen,
-                       &counter, &depth_scr, &scan_tmp, &dv_scr})
+                       &counter, &depth_scr, &scan_tmp, &dv_scr, &cls, &stale})
             b->release();
         for (auto& b : etree) b.release();
         for (auto& b : enpar) b.release();
     }
 };
+
+// Primary edge table, CDF and edge hierarchy of view v from the scene's
+// current vertices, copied into the batch's buffers (same device addresses
+// on every call); updates the view's host-side arguments. Synchronises.
+static drStatus build_batch_view(drBatch_t* b, int v, hipStream_t st) {
+    drScene_t* s = b->s;
+    int E = s->E;
+    const Cam& cam = b->cams[v];
+    s->tree_valid = false;
+    drStatus r = build_view_edges(s, cam, b->keys[v], b->tree, st);
+    if (r != DR_SUCCESS) return r;
+    PEdge* pe_v = b->pe.as<PEdge>() + (size_t)v * E;
+    double* pcdf_v = b->pcdf.as<double>() + (size_t)v * (E + 1);
+    if (hipMemcpyAsync(pe_v, s->pe.p, sizeof(PEdge) * E, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(pcdf_v, s->pcdf.p, sizeof(double) * (E + 1), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return DR_ERROR_DEVICE;
+    TreeView tv{};
+    tv.cam = cam.c;
+    tv.valid = 0;
+    int mh[2] = {0, 0}, bh[2] = {0, 0};
+    if (b->tree) {
+        int nn = s->etree_nodes;
+        if (nn > std::max(E, 1)) return DR_ERROR_DEVICE;
+        if (hipMemcpyAsync(b->etree[v].p, s->etree.p, sizeof(ETNode) * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(b->enpar[v].p, s->enpar.p, sizeof(int) * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(b->eleaf.as<int>() + (size_t)v * E, s->eleaf.p, sizeof(int) * E, hipMemcpyDeviceToDevice,
+                           st) != hipSuccess ||
+            hipMemcpyAsync(b->elist.as<int>() + (size_t)v * 2 * E, s->elist_s.p, sizeof(int) * 2 * E,
+                           hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(b->eparent.as<int>() + (size_t)v * 4 * E, s->eparent.p, sizeof(int) * 4 * E,
+                           hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return DR_ERROR_DEVICE;
+        for (int h = 0; h < 2; ++h) { mh[h] = s->tree_m[h]; bh[h] = s->tree_base[h]; }
+        tv.nodes = b->etree[v].as<ETNode>();
+        tv.eleaf = b->eleaf.as<int>() + (size_t)v * E;
+        tv.enpar = b->enpar[v].as<int>();
+        tv.valid = (mh[0] + mh[1]) > 0 ? 1 : 0;
+    }
+    // the scene's buffers are overwritten by the next view: wait before reuse
+    if (hipStreamSynchronize(st) != hipSuccess) return DR_ERROR_DEVICE;
+    b->m0[v] = mh[0]; b->m1[v] = mh[1]; b->base0[v] = bh[0]; b->base1[v] = bh[1];
+    b->hv[v].tv = tv;
+    b->hv[v].pe = pe_v;
+    b->hv[v].pcdf = pcdf_v;
+    return DR_SUCCESS;
+}
 
 #define B_CHECK(x)                                    \
     do {                                              \
@@ -52,7 +101,7 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
     for (int v = 0; v < n; ++v) {
         const drRenderOptions& o = opts[v];
         if (!valid_camera(&cams[v]) || !valid_options(&o) || !images[v] || !d_images[v]) return DR_ERROR_INVALID_VALUE;
-        if (o.max_depth != opts[0].max_depth || o.unit_mask || o.edge_pdf || o.edge_stats || o.edge_mix != 0.0f || o.aov != 0)
+        if (o.max_depth != opts[0].max_depth || o.edge_pdf || o.edge_stats || o.edge_mix != 0.0f || o.aov != 0)
             return DR_ERROR_INVALID_VALUE;
     }
     drBatch_t* b = new drBatch_t();
@@ -101,63 +150,45 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
     B_ALLOC(b->dv_scr, sizeof(float) * (size_t)b->shards * (3 * (size_t)s->V + s->T));
     b->etree.resize(n);
     b->enpar.resize(n);
-    std::vector<BatchView> hv(n);
+    b->hv.resize(n);
+    b->m0.assign(n, 0); b->m1.assign(n, 0); b->base0.assign(n, 0); b->base1.assign(n, 0);
+    if (b->tree) {
+        // room for the largest hierarchy pair any vertex positions can give
+        // (at most E nodes), so rebuilds keep every device address
+        for (int v = 0; v < n; ++v) {
+            B_ALLOC(b->etree[v], sizeof(ETNode) * (size_t)std::max(E, 1));
+            B_ALLOC(b->enpar[v], sizeof(int) * (size_t)std::max(E, 1));
+        }
+    }
+    B_ALLOC(b->cls, (size_t)n * std::max(E, 1));
+    B_ALLOC(b->stale, sizeof(int));
     for (int v = 0; v < n; ++v) {
         const Cam& cam = b->cams[v];
         ViewKey key = make_key(s, cams[v], opts[v]);
         key.spp = 0; key.seed = 0; key.view = 0; key.mask = nullptr; key.depth = 0;
-        s->tree_valid = false;
-        drStatus r = build_view_edges(s, cam, key, b->tree, st);
-        if (r != DR_SUCCESS) return fail(r);
-        PEdge* pe_v = b->pe.as<PEdge>() + (size_t)v * E;
-        double* pcdf_v = b->pcdf.as<double>() + (size_t)v * (E + 1);
-        B_CHECK(hipMemcpyAsync(pe_v, s->pe.p, sizeof(PEdge) * E, hipMemcpyDeviceToDevice, st));
-        B_CHECK(hipMemcpyAsync(pcdf_v, s->pcdf.p, sizeof(double) * (E + 1), hipMemcpyDeviceToDevice, st));
-        TreeView tv{};
-        tv.cam = cam.c;
-        tv.valid = 0;
-        int mh[2] = {0, 0}, bh[2] = {0, 0};
-        if (b->tree) {
-            int nn = s->etree_nodes;
-            B_ALLOC(b->etree[v], sizeof(ETNode) * (size_t)nn);
-            B_ALLOC(b->enpar[v], sizeof(int) * (size_t)nn);
-            B_CHECK(hipMemcpyAsync(b->etree[v].p, s->etree.p, sizeof(ETNode) * nn, hipMemcpyDeviceToDevice, st));
-            B_CHECK(hipMemcpyAsync(b->enpar[v].p, s->enpar.p, sizeof(int) * nn, hipMemcpyDeviceToDevice, st));
-            B_CHECK(hipMemcpyAsync(b->eleaf.as<int>() + (size_t)v * E, s->eleaf.p, sizeof(int) * E, hipMemcpyDeviceToDevice, st));
-            B_CHECK(hipMemcpyAsync(b->elist.as<int>() + (size_t)v * 2 * E, s->elist_s.p, sizeof(int) * 2 * E,
-                                   hipMemcpyDeviceToDevice, st));
-            B_CHECK(hipMemcpyAsync(b->eparent.as<int>() + (size_t)v * 4 * E, s->eparent.p, sizeof(int) * 4 * E,
-                                   hipMemcpyDeviceToDevice, st));
-            for (int h = 0; h < 2; ++h) { mh[h] = s->tree_m[h]; bh[h] = s->tree_base[h]; }
-            tv.nodes = b->etree[v].as<ETNode>();
-            tv.eleaf = b->eleaf.as<int>() + (size_t)v * E;
-            tv.enpar = b->enpar[v].as<int>();
-            tv.valid = (mh[0] + mh[1]) > 0 ? 1 : 0;
-        }
-        // the scene's buffers are overwritten by the next view: wait before reuse
-        B_CHECK(hipStreamSynchronize(st));
-        b->m0.push_back(mh[0]); b->m1.push_back(mh[1]); b->base0.push_back(bh[0]); b->base1.push_back(bh[1]);
+        b->keys.push_back(key);
         RenderArgs a = render_args(s, cam, opts[v]);
         a.counters = nullptr;
-        a.mask = nullptr;
         a.debug_unit = -1;
         a.ck_tri = b->ck_tri.as<int>() + 3 * ck_off[v];
         a.ck_x = b->ck_x.as<float>() + 9 * ck_off[v];
         a.ck_vis = b->ck_vis.as<uint8_t>() + ck_off[v];
-        BatchView& bv = hv[v];
+        BatchView& bv = b->hv[v];
         bv.k = cam;
         bv.a = a;
-        bv.tv = tv;
-        bv.pe = pe_v;
-        bv.pcdf = pcdf_v;
         bv.image = images[v];
         bv.d_image = d_images[v];
         bv.camacc = b->camacc.as<float>() + 12 * (size_t)v * b->shards;
         bv.reduce = (BS % opts[v].spp) == 0 ? 1 : 0;
+        drStatus r = build_batch_view(b, v, st);
+        if (r != DR_SUCCESS) return fail(r);
     }
     s->tree_valid = false;
-    B_CHECK(hipMemcpyAsync(b->views.p, hv.data(), sizeof(BatchView) * n, hipMemcpyHostToDevice, st));
+    B_CHECK(hipMemcpyAsync(b->views.p, b->hv.data(), sizeof(BatchView) * n, hipMemcpyHostToDevice, st));
     B_CHECK(hipMemcpyAsync(b->boff.p, boff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st));
+    B_CHECK(hipMemsetAsync(b->stale.p, 0, sizeof(int), st));
+    drStatus r = launch_batch_class(s, b->views.as<BatchView>(), n, b->cls.as<uint8_t>(), 0, b->stale.as<int>(), st);
+    if (r != DR_SUCCESS) return fail(r);
     B_CHECK(hipStreamSynchronize(st));
     *out = b;
     return DR_SUCCESS;
@@ -216,6 +247,33 @@ extern "C" drStatus drBatchRefit(drBatch b, hipStream_t st) {
                                 b->counter.as<int>(), b->depth_scr.as<int>(), b->scan_tmp.p, b->scan_bytes, st);
         if (r != DR_SUCCESS) return r;
     }
+    if (b->tree)
+        return launch_batch_class(s, b->views.as<BatchView>(), b->n, b->cls.as<uint8_t>(), 1, b->stale.as<int>(), st);
+    return DR_SUCCESS;
+}
+
+extern "C" drStatus drBatchCheckHierarchy(drBatch b, int32_t* rebuilt, hipStream_t st) {
+    if (!b || !rebuilt) return DR_ERROR_INVALID_VALUE;
+    *rebuilt = 0;
+    drScene_t* s = b->s;
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, b->stale.p, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return DR_ERROR_DEVICE;
+    if (!flag || !b->tree) return DR_SUCCESS;
+    for (int v = 0; v < b->n; ++v) {
+        b->keys[v].version = s->version;
+        drStatus r = build_batch_view(b, v, st);
+        if (r != DR_SUCCESS) return r;
+    }
+    s->tree_valid = false;
+    if (hipMemcpyAsync(b->views.p, b->hv.data(), sizeof(BatchView) * b->n, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemsetAsync(b->stale.p, 0, sizeof(int), st) != hipSuccess)
+        return DR_ERROR_DEVICE;
+    drStatus r = launch_batch_class(s, b->views.as<BatchView>(), b->n, b->cls.as<uint8_t>(), 0, b->stale.as<int>(), st);
+    if (r != DR_SUCCESS) return r;
+    if (hipStreamSynchronize(st) != hipSuccess) return DR_ERROR_DEVICE;
+    *rebuilt = 1;
     return DR_SUCCESS;
 }
 

@@ -561,6 +561,31 @@ __global__ void k_edge_class(SceneView s, v3 cam, int* __restrict__ f1, int* __r
     f2[i] = c == 2;
 }
 
+// Class of every edge of every batch view (0 in no hierarchy, 1 first, 2
+// second), computed as k_edge_class does. check = 0 stores it; check = 1
+// compares with the stored class and raises *stale where the kept hierarchy
+// cannot represent the current one: an edge now in the first class but kept
+// outside it (missing, or pruned by the second hierarchy's test, which
+// assumes a non-silhouette from the camera), or an edge now in the second
+// class but in no hierarchy. Edges that left a class only waste samples.
+__global__ void k_batch_class(SceneView s, const BatchView* __restrict__ views, int n, uint8_t* __restrict__ cls, int check,
+                              int* __restrict__ stale) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int v = blockIdx.y;
+    if (i >= s.E || v >= n) return;
+    uint8_t kind = s.ekind[i];
+    uint8_t c = 0;
+    if (kind == 1) c = 1;
+    else if (kind == 2) c = silhouette_from(s, s.edges[i], views[v].k.c) ? 1 : 2;
+    uint8_t* slot = cls + (size_t)v * s.E + i;
+    if (!check) {
+        *slot = c;
+        return;
+    }
+    uint8_t kept = *slot;
+    if ((c == 1 && kept != 1) || (c == 2 && kept == 0)) *stale = 1;
+}
+
 __global__ void k_edge_compact(const int* __restrict__ f1, const int* __restrict__ f2, const int* __restrict__ p1,
                                const int* __restrict__ p2, int E, int* __restrict__ l1, int* __restrict__ l2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -877,6 +902,14 @@ drStatus refit_view(drScene_t* s, const Cam& cam, PEdge* pe, double* plen, doubl
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 
+drStatus launch_batch_class(drScene_t* s, const BatchView* views, int n, uint8_t* cls, int check, int* stale,
+                            hipStream_t st) {
+    if (s->E == 0 || n == 0) return DR_SUCCESS;
+    dim3 g(blocks(s->E, 256), n);
+    k_batch_class<<<g, 256, 0, st>>>(s->view(), views, n, cls, check, stale);
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
 size_t refit_scan_bytes(int E) {
     size_t tmp = 0;
     (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (double*)nullptr, (double*)nullptr, E, (hipStream_t)0);
@@ -901,6 +934,16 @@ drStatus refit_scene(drScene_t* s, const float* vertices, hipStream_t st) {
         k_bvh_refit<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->ids_s.as<int>(),
                                                   s->parent.as<int>(), s->bvh.as<BvhNode>(), s->ids.as<int>());
     }
+    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
+}
+
+// Edge kinds from the current vertices and albedos (after an albedo update:
+// nothing else of the scene depends on the albedos). Kernel launch only.
+drStatus refresh_edge_kinds(drScene_t* s, hipStream_t st) {
+    if (s->E > 0)
+        k_edge_kind<<<blocks(s->E, 256), 256, 0, st>>>(s->edges.as<int4>(), s->E, s->P.as<float>(), s->I.as<int>(),
+                                                       s->alb.as<float>(), s->emi.as<float>(), s->smooth ? 1 : 0,
+                                                       s->ekind.as<uint8_t>());
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 

@@ -87,6 +87,8 @@ struct drScene_t {
     // split backward: side-path queries, their radiances, per-(vertex, unit) query index, count
     dr::Buf sq, sres, sqidx, scount, svtri, svx;
     bool split_backward = true;
+    dr::Buf pq, pcount;              // primary edge samples whose sides hit different triangles
+    bool split_primary = true;
     hipStream_t last_stream = nullptr;
     int device = 0;
     // measurement
@@ -109,7 +111,12 @@ drStatus refit_view(drScene_t* s, const Cam& cam, PEdge* pe, double* plen, doubl
                     const int* list_s, const int* parent, const int m[2], const int base[2], int* counter, int* depth,
                     void* scan_tmp, size_t scan_bytes, hipStream_t st);
 size_t refit_scan_bytes(int E);
+// Stores (check = 0) or checks (check = 1, raising *stale) every batch view's
+// edge classes against its kept hierarchy; cls is [n][E].
+drStatus launch_batch_class(drScene_t* s, const BatchView* views, int n, uint8_t* cls, int check, int* stale,
+                            hipStream_t st);
 drStatus refit_scene(drScene_t* s, const float* vertices, hipStream_t st);
+drStatus refresh_edge_kinds(drScene_t* s, hipStream_t st);
 Cam make_cam(const drCamera& c);
 
 // dr_render.hip

@@ -1,1221 +1,10 @@
-// Forward and backward kernels of the edge-sampling differentiable path
-// tracer (thesis Ch. 5). One lane per unit: a unit is one pixel sample (its
-// path, interior adjoint and one secondary edge sample per path vertex) plus
-// one primary edge sample. Blocks are one 64-lane wave; each lane's BVH
-// traversal stack lives in LDS.
-//
-// Measure convention of the interior term: the screen sample, every sampled
-// world direction and every sampling pdf are held fixed (the integrals are
-// over screen space and over the sphere of directions at each vertex); hit
-// points move by ray-plane intersection with their triangles. The boundary
-// terms use the matching measures: screen-space edges (eq. mc) and
-// direction-space edges at each vertex (eq. dirac_3d_edge in the solid-angle
-// measure; its endpoint terms equal the thesis's area form exactly).
-#include <cstdlib>
-#include <type_traits>
-
-#include "dr_args.h"
-#include "dr_host.h"
-#include "dr_path.h"
+// Backward pass orchestration: gradient shards, the learned-proposal
+// mixture tables, primary edge samples, path backward at the kernel depth
+// that covers max_depth, shard reduction and the camera adjoint.
+#include "dr_kernels.h"
+#include "dr_launch.h"
 
 namespace dr {
-
-__device__ inline void unit_pixel(const Cam& k, const RenderArgs& a, int m, int& pix, int& px, int& py, uint32_t& sid) {
-    pix = m / a.spp;
-    int smp = m - pix * a.spp;
-    int pxr = pix % a.Ww, pyr = pix / a.Ww;
-    px = k.x0 + pxr;
-    py = k.y0 + pyr;
-    sid = ((uint32_t)py * (uint32_t)k.W + (uint32_t)px) * (uint32_t)a.spp + (uint32_t)smp;
-}
-
-__device__ inline void flush_work(const NoWork&, unsigned long long*) {}
-
-__device__ inline void flush_work(const Work& w, unsigned long long* c) {
-    if (!c) return;
-    uint32_t v[5] = {w.nodes, w.tris, w.tnodes, w.atom, w.rays};
-    for (int i = 0; i < 5; ++i) {
-        uint32_t t = v[i];
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, BS);
-        if (threadIdx.x == 0 && t) atomicAdd(&c[i], (unsigned long long)t);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// forward
-// ---------------------------------------------------------------------------
-// One wave of units [mbase, mbase + 64) of one view; stk: the block's LDS
-// traversal stacks.
-template <int STK, bool CNT>
-__device__ __forceinline__ void forward_body(const SceneView& s, const Cam& k, const RenderArgs& a, float* __restrict__ image,
-                                             int reduce, int mbase, int* stk) {
-    int lane = threadIdx.x;
-    int* my = stk + lane;
-    int m = mbase + lane;
-    float L = 0.0f;
-    int pix = 0;
-    typename std::conditional<CNT, Work, NoWork>::type wk;
-    if (m < a.M) {
-        int px, py;
-        uint32_t sid;
-        unit_pixel(k, a, m, pix, px, py, sid);
-        bool act = !a.mask || a.mask[m];
-        int ckt0 = -1, ckt1 = -1, ckt2 = -1;
-        v3 ckx0 = {0, 0, 0}, ckx1 = {0, 0, 0}, ckx2 = {0, 0, 0};
-        uint8_t vis = 0;
-        if (act) {
-            Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
-            float4 j = rc.block(0);
-            v3 d = cam_dir(k, px + j.x, py + j.y);
-            Hit h = trace_closest(s, k.c, d, k.nearc, 3.0e38f, my, BS, wk);
-            if (h.tri < 0) {
-                L = s.background;
-            } else {
-                int tri = h.tri;
-                TriGeom g = tri_geom(s, tri);
-                v3 x = hit_point(g, k.c, d);
-                bool front = dot(d, cross(g.e1, g.e2)) < 0.0f;
-                L = emitted(s, tri, front);
-                ckt0 = tri;
-                ckx0 = x;
-                float beta = 1.0f;
-                for (int kk = 1; kk <= a.depth; ++kk) {
-                    v3 ns = shading_normal(s, tri, g, x);
-                    if (!front) ns = -ns;
-                    float rho = s.alb[tri];
-                    if (rho == 0.0f) break;
-                    NeeSample q = nee_sample(s, rc.block(2 * kk - 1), x, ns);
-                    if (q.K > 0.0f && !trace_any(s, x, q.w, s.tmin, q.r * (1.0f - kShadowEnd), my, BS, wk)) {
-                        L += beta * rho * dot(ns, q.w) * q.K;
-                        vis |= (uint8_t)(1u << (kk - 1));
-                    }
-                    if (kk == a.depth) break;
-                    float4 ub = rc.block(2 * kk);
-                    v3 w = cosine_dir(ns, ub.x, ub.y);
-                    if (dot(ns, w) <= 0.0f) break;
-                    Hit h2 = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, wk);
-                    if (h2.tri < 0) break;
-                    beta *= rho;
-                    tri = h2.tri;
-                    g = tri_geom(s, tri);
-                    x = hit_point(g, x, w);
-                    front = dot(w, cross(g.e1, g.e2)) < 0.0f;
-                    if (kk == 1) { ckt1 = tri; ckx1 = x; }
-                    if (kk == 2) { ckt2 = tri; ckx2 = x; }
-                }
-            }
-        }
-        if (a.ck_tri) {
-            a.ck_tri[m] = ckt0;
-            a.ck_tri[a.M + m] = ckt1;
-            a.ck_tri[2 * (size_t)a.M + m] = ckt2;
-            float* cx = a.ck_x + 3 * (size_t)m;
-            cx[0] = ckx0.x; cx[1] = ckx0.y; cx[2] = ckx0.z;
-            float* cy = a.ck_x + 3 * ((size_t)a.M + m);
-            cy[0] = ckx1.x; cy[1] = ckx1.y; cy[2] = ckx1.z;
-            float* cz = a.ck_x + 3 * (2 * (size_t)a.M + m);
-            cz[0] = ckx2.x; cz[1] = ckx2.y; cz[2] = ckx2.z;
-            a.ck_vis[m] = vis;
-        }
-    }
-    flush_work(wk, a.counters);
-    float v = L / (float)a.spp;
-    if (reduce) {
-        // a.spp divides 64: lanes of one pixel are consecutive, reduce in-wave
-        for (int off = a.spp >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, BS);
-        if (m < a.M && (lane % a.spp) == 0) image[pix] = v;
-    } else if (m < a.M) {
-        atomicAdd(&image[pix], v);
-    }
-}
-
-template <int STK, bool CNT>
-__global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a, float* __restrict__ image, int reduce) {
-    __shared__ int stk[STK * BS];
-    forward_body<STK, CNT>(s, k, a, image, reduce, blockIdx.x * BS, stk);
-}
-
-// Geometry buffers (Ch. 5, Results): channel a.aov (1..7) of the first hit of
-// each camera ray, or all seven (a.aov = 8; image [7][Hw][Ww]); 0 where the
-// ray escapes. Stores the first-hit checkpoint the backward pass reuses.
-template <int STK>
-__global__ __launch_bounds__(BS) void k_forward_aov(SceneView s, Cam k, RenderArgs a, float* __restrict__ image,
-                                                    int reduce) {
-    __shared__ int stk[STK * BS];
-    int lane = threadIdx.x;
-    int* my = stk + lane;
-    int m = blockIdx.x * BS + lane;
-    NoWork wk;
-    float v[7] = {0, 0, 0, 0, 0, 0, 0};
-    int pix = 0;
-    if (m < a.M) {
-        int px, py;
-        uint32_t sid;
-        unit_pixel(k, a, m, pix, px, py, sid);
-        int ckt = -1;
-        v3 ckx = {0, 0, 0};
-        if (!a.mask || a.mask[m]) {
-            Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
-            float4 j = rc.block(0);
-            v3 d = cam_dir(k, px + j.x, py + j.y);
-            Hit h = trace_closest(s, k.c, d, k.nearc, 3.0e38f, my, BS, wk);
-            if (h.tri >= 0) {
-                TriGeom g = tri_geom(s, h.tri);
-                v3 x = hit_point(g, k.c, d);
-                if (a.aov == 8) aov_values(s, h.tri, g, x, d, v);
-                else v[0] = aov_value(s, a.aov, h.tri, g, x, d);
-                ckt = h.tri;
-                ckx = x;
-            }
-        }
-        if (a.ck_tri) {
-            a.ck_tri[m] = ckt;
-            a.ck_tri[a.M + m] = -1;
-            a.ck_tri[2 * (size_t)a.M + m] = -1;
-            float* cx = a.ck_x + 3 * (size_t)m;
-            cx[0] = ckx.x; cx[1] = ckx.y; cx[2] = ckx.z;
-            a.ck_vis[m] = 0;
-        }
-    }
-    int nch = a.aov == 8 ? 7 : 1;
-    long npix = (long)a.Ww * (k.y1 - k.y0);
-#pragma unroll
-    for (int c = 0; c < 7; ++c) {
-        if (c >= nch) break;
-        float val = v[c] / (float)a.spp;
-        if (reduce) {
-            for (int off = a.spp >> 1; off > 0; off >>= 1) val += __shfl_xor(val, off, BS);
-            if (m < a.M && (lane % a.spp) == 0) image[c * npix + pix] = val;
-        } else if (m < a.M) {
-            atomicAdd(&image[c * npix + pix], val);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// adjoint helpers
-// ---------------------------------------------------------------------------
-struct CamAcc { v3 f, r, u, c; };
-
-__device__ inline void atomic_add3(float* p, int i, v3 v) {
-    if (v.x != 0.0f) atomicAdd(&p[3 * i], v.x);
-    if (v.y != 0.0f) atomicAdd(&p[3 * i + 1], v.y);
-    if (v.z != 0.0f) atomicAdd(&p[3 * i + 2], v.z);
-}
-
-// Adjoint of the projection to pixels.
-__device__ inline v3 project_adj(const Cam& k, v3 P, float gsx, float gsy, CamAcc& ca) {
-    v3 q = P - k.c;
-    float z = dot(q, k.f), xc = dot(q, k.r), yc = dot(q, k.u);
-    float ax = k.W * 0.5f / (k.asp * k.th), ay = k.H * 0.5f / k.th;
-    float gxc = gsx * ax / z;
-    float gyc = -gsy * ay / z;
-    float gz = -gsx * ax * xc / (z * z) + gsy * ay * yc / (z * z);
-    v3 gq = k.f * gz + k.r * gxc + k.u * gyc;
-    ca.f += q * gz;
-    ca.r += q * gxc;
-    ca.u += q * gyc;
-    ca.c -= gq;
-    return gq;
-}
-
-// Adjoint of a* = a + (b - a) s, s = (zd - za)/(zb - za), zd = max(near, zb/2).
-__device__ inline void nearclip_adj(const Cam& k, v3 a, v3 b, v3 g, v3& ga, v3& gb, CamAcc& ca) {
-    float za = dot(a - k.c, k.f), zb = dot(b - k.c, k.f);
-    float D = zb - za;
-    bool half = 0.5f * zb > k.nearc;
-    float zd = half ? 0.5f * zb : k.nearc;
-    float s = (zd - za) / D;
-    ga += g * (1.0f - s);
-    gb += g * s;
-    float gs = dot(g, b - a);
-    float gza = gs * (s - 1.0f) / D, gzb = gs * ((half ? 0.5f : 0.0f) - s) / D;
-    ga += k.f * gza;
-    gb += k.f * gzb;
-    ca.c -= k.f * (gza + gzb);
-    ca.f += (a - k.c) * gza + (b - k.c) * gzb;
-}
-
-// Adjoint of x = o + d t, t = (p0 - o).n / (d.n), n = e1 x e2.
-__device__ inline void ray_plane_adj(const TriGeom& g, v3 o, v3 d, v3 gx, v3& go, v3& gd, v3& gp0, v3& gp1, v3& gp2) {
-    v3 n = cross(g.e1, g.e2);
-    float den = dot(d, n);
-    float num = dot(g.p0 - o, n);
-    float t = num / den;
-    go += gx;
-    gd += gx * t;
-    float gt = dot(gx, d);
-    float gnum = gt / den, gden = -gt * t / den;
-    gp0 += n * gnum;
-    go -= n * gnum;
-    v3 gn = (g.p0 - o) * gnum + d * gden;
-    gd += n * gden;
-    v3 ge1 = cross(g.e2, gn), ge2 = cross(gn, g.e1);
-    gp1 += ge1;
-    gp2 += ge2;
-    gp0 -= ge1 + ge2;
-}
-
-// Adjoint of the shading normal (unoriented) w.r.t. the hit point and the
-// triangle vertices; gns is dL/d(normal before orientation).
-__device__ inline void shading_normal_adj(const SceneView& s, int id, const TriGeom& g, v3 x, v3 gns, v3& gx, v3& gp0, v3& gp1,
-                                          v3& gp2) {
-    v3 n = cross(g.e1, g.e2);
-    v3 gn = {0, 0, 0}, ge1 = {0, 0, 0}, ge2 = {0, 0, 0};
-    if (!s.N) {
-        gn = nrm_adj(n, gns);
-    } else {
-        v3 w = x - g.p0;
-        float nn = dot(n, n);
-        v3 c1 = cross(w, g.e2), c2 = cross(g.e1, w);
-        float b1 = dot(c1, n) / nn, b2 = dot(c2, n) / nn;
-        int i0 = s.I[3 * id], i1 = s.I[3 * id + 1], i2 = s.I[3 * id + 2];
-        v3 N0 = ld3(s.N, i0), N1 = ld3(s.N, i1), N2 = ld3(s.N, i2);
-        v3 mv = N0 * (1.0f - b1 - b2) + N1 * b1 + N2 * b2;
-        v3 gm = nrm_adj(mv, gns);
-        float gb1 = dot(gm, N1 - N0), gb2 = dot(gm, N2 - N0);
-        float gq1 = gb1 / nn, gq2 = gb2 / nn;
-        float gnn = -(gb1 * b1 + gb2 * b2) / nn;
-        v3 gc1 = n * gq1, gc2 = n * gq2;
-        gn += c1 * gq1 + c2 * gq2 + n * (2.0f * gnn);
-        v3 gw = cross(g.e2, gc1) + cross(gc2, g.e1);
-        ge2 += cross(gc1, w);
-        ge1 += cross(w, gc2);
-        gx += gw;
-        gp0 -= gw;
-    }
-    ge1 += cross(g.e2, gn);
-    ge2 += cross(gn, g.e1);
-    gp1 += ge1;
-    gp2 += ge2;
-    gp0 -= ge1 + ge2;
-}
-
-__device__ inline float wave_sum(float v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, BS);
-    return v;
-}
-
-__device__ inline float wave_sum_all(float v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, BS);
-    return v;
-}
-
-// Gradient scatter with in-wave pre-reduction. Lanes holding the same key
-// (an edge or a triangle) are summed with cross-lane shuffles and one lane
-// issues the atomics, which removes same-address atomic contention when the
-// lanes of a wave work on the same primitive (all samples of a pixel, or the
-// stratified primary edge samples). After `max_groups` distinct keys the
-// remaining lanes add their values directly. Must be called by all lanes.
-template <int N, class Dest>
-__device__ inline void scatter_grouped(bool valid, int key, const float (&vals)[N], int max_groups, Dest dest) {
-    const int lane = threadIdx.x;
-    unsigned long long active = __ballot(valid);
-    for (int it = 0; active; ++it) {
-        if (it == max_groups) {
-            if ((active >> lane) & 1ull)
-#pragma unroll
-                for (int i = 0; i < N; ++i)
-                    if (vals[i] != 0.0f) atomicAdd(dest(key, i), vals[i]);
-            break;
-        }
-        int leader = __ffsll(active) - 1;
-        int lkey = __shfl(key, leader, BS);
-        bool mine = ((active >> lane) & 1ull) && key == lkey;
-        unsigned long long grp = __ballot(mine);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            float v = wave_sum_all(mine ? vals[i] : 0.0f);
-            if (lane == leader && v != 0.0f) atomicAdd(dest(lkey, i), v);
-        }
-        active &= ~grp;
-    }
-}
-
-__device__ inline void flush_cam(const CamAcc& ca, float* camacc) {
-    float v[12] = {ca.f.x, ca.f.y, ca.f.z, ca.r.x, ca.r.y, ca.r.z, ca.u.x, ca.u.y, ca.u.z, ca.c.x, ca.c.y, ca.c.z};
-    for (int i = 0; i < 12; ++i) {
-        float t = wave_sum(v[i]);
-        if (threadIdx.x == 0 && t != 0.0f) atomicAdd(&camacc[i], t);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// primary edge samples (eq. mc): one per unit
-// ---------------------------------------------------------------------------
-template <int STK, bool CNT, bool MIX, bool AOV = false>
-__device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, const RenderArgs& a, const PEdge* __restrict__ pe,
-                                             const double* __restrict__ cdf, const float* __restrict__ d_image,
-                                             float* __restrict__ dV, float* __restrict__ camacc, const MixArgs& mx,
-                                             int mbase, int* stk) {
-    int lane = threadIdx.x;
-    int* my = stk + lane;
-    int m = mbase + lane;
-    CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    typename std::conditional<CNT, Work, NoWork>::type wk;
-    double total = cdf[s.E];
-    bool have = false;
-    int key = -1;
-    float gv[6] = {0, 0, 0, 0, 0, 0};
-    if (m < a.M && (!a.mask || a.mask[m]) && total > 0.0) {
-        Rng rp{(uint32_t)m, a.view, kTagPedge, a.k0, a.k1};
-        float4 b0 = rp.block(0);
-        // stratified edge choice: unit m draws its uniform in [m/M, (m+1)/M), so
-        // the lanes of a wave take neighbouring edges in CDF order
-        bool mixp = MIX && mx.prim;
-        int ei = pick_cdf_d(mixp ? mx.mcdf : cdf, s.E, ((double)m + (double)b0.x) / (double)a.M);
-        // 1 / (P(edge) p(point | edge)), the point uniform on the clipped segment
-        double inv_p = total, p_edge = 0.0;
-        bool live = true;
-        if (MIX) {
-            double l = mx.plen[ei];
-            p_edge = mixp ? ((1.0 - (double)mx.mix) * l / total + (double)mx.mix * (double)mx.q[ei]) / mx.mcdf[s.E]
-                          : l / total;
-            live = l > 0.0;
-            if (live) inv_p = l / p_edge;
-        }
-        if (live) {
-        PEdge p = pe[ei];
-        float t = b0.y;
-        float x = p.Ac[0] + (p.Bc[0] - p.Ac[0]) * t, y = p.Ac[1] + (p.Bc[1] - p.Ac[1]) * t;
-        int4 e = s.edges[ei];
-        v3 va = ld3(s.P, e.x), vb = ld3(s.P, e.y);
-        float za = dot(va - k.c, k.f), zb = dot(vb - k.c, k.f);
-        v3 ac = za < k.nearc ? alpha_point(k, va, vb, za, zb) : va;
-        v3 bc = zb < k.nearc ? alpha_point(k, vb, va, zb, za) : vb;
-        float Ax, Ay, Bx, By;
-        project(k, ac, Ax, Ay);
-        project(k, bc, Bx, By);
-        float dx = Ax - Bx, dy = Ay - By;
-        float nl = sqrtf(dx * dx + dy * dy);
-        float nx = (Ay - By) / nl, ny = (Bx - Ax) / nl;
-        v3 du = cam_dir(k, x + kEpsPx * nx, y + kEpsPx * ny), dl = cam_dir(k, x - kEpsPx * nx, y - kEpsPx * ny);
-        int ix = min(max((int)floorf(x), k.x0), k.x1 - 1);
-        int iy = min(max((int)floorf(y), k.y0), k.y1 - 1);
-        const float* dI = d_image + (iy - k.y0) * a.Ww + (ix - k.x0);
-        // loss gradient times the jump of the pixel function across the edge
-        float jump = 0.0f;
-        bool jumps;
-        if (AOV) {
-            jump = aov_jump(s, a.aov, k.c, du, dl, k.nearc, dI, a.Ww * (k.y1 - k.y0), my, BS, wk);
-            jumps = jump != 0.0f;
-        } else {
-            float fu, fl;
-            radiance_pair(s, rp, 0, k.c, du, dl, k.nearc, true, a.depth, my, BS, wk, fu, fl);
-            jumps = fu != fl;
-            if (jumps) jump = dI[0] * (fu - fl);
-        }
-        if (m == a.debug_unit)
-            printf("punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g n %.9g %.9g jump %.9g total %.9g\n", m, ei, x, y,
-                   Ax, Ay, Bx, By, nx, ny, jump, total);
-        if (jumps) {
-            float w = jump * (float)(inv_p / (double)a.M) / nl;
-            // d alpha / d(a, b) (eq. redner_dirac_jacobian) at the sample point
-            float gax = w * (By - y), gay = w * (x - Bx);
-            float gbx = w * (y - Ay), gby = w * (Ax - x);
-            v3 gac = project_adj(k, ac, gax, gay, ca);
-            v3 gbc = project_adj(k, bc, gbx, gby, ca);
-            v3 ga = {0, 0, 0}, gb = {0, 0, 0};
-            if (za < k.nearc) nearclip_adj(k, va, vb, gac, ga, gb, ca);
-            else ga += gac;
-            if (zb < k.nearc) nearclip_adj(k, vb, va, gbc, gb, ga, ca);
-            else gb += gbc;
-            have = true;
-            key = ei;
-            gv[0] = ga.x; gv[1] = ga.y; gv[2] = ga.z;
-            gv[3] = gb.x; gv[4] = gb.y; gv[5] = gb.z;
-            wk.atomics(6);
-            if (MIX && mx.estats) {
-                float c2 = 0.0f;
-#pragma unroll
-                for (int i = 0; i < 6; ++i) c2 += gv[i] * gv[i];
-                atomicAdd(&mx.estats[ei], (float)p_edge * c2);
-            }
-        }
-        }
-    }
-    scatter_grouped(have, key, gv, 4, [&](int ek, int i) {
-        int4 e = s.edges[ek];
-        return &dV[3 * (i < 3 ? e.x : e.y) + (i % 3)];
-    });
-    flush_work(wk, a.counters);
-    flush_cam(ca, camacc);
-}
-
-// Five waves per SIMD (at most 96 VGPRs, a few spilled): measured faster
-// than four for this kernel, unlike for the path backward kernels.
-template <int STK, bool CNT, bool MIX, bool AOV = false>
-__global__ __launch_bounds__(BS, 5) void k_primary(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
-                                                const double* __restrict__ cdf, const float* __restrict__ d_image,
-                                                float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
-    __shared__ int stk[STK * BS];
-    int sh = blockIdx.x & (a.gshards - 1);
-    primary_body<STK, CNT, MIX, AOV>(s, k, a, pe, cdf, d_image, dV + sh * a.gstride, camacc + 12 * sh, mx, blockIdx.x * BS, stk);
-}
-
-// ---------------------------------------------------------------------------
-// edge hierarchy descent (Edge selection): one uniform per level, explicit pdf
-// ---------------------------------------------------------------------------
-__device__ inline bool vsphere_prune(const ETChild& c, v3 pc) {
-    v3 sc = pc * 0.5f;
-    float r2 = dot(pc, pc) * 0.25f;
-    const float sv[3] = {sc.x, sc.y, sc.z};
-    bool out[2], in[2];
-    for (int f = 0; f < 2; ++f) {
-        const float* lo = f == 0 ? c.hlo0 : c.hlo1;
-        const float* hi = f == 0 ? c.hhi0 : c.hhi1;
-        float d2 = 0.0f, far2 = 0.0f;
-        for (int k = 0; k < 3; ++k) {
-            float d = sv[k] < lo[k] ? lo[k] - sv[k] : (sv[k] > hi[k] ? sv[k] - hi[k] : 0.0f);
-            d2 += d * d;
-            float fa = fmaxf(fabsf(lo[k] - sv[k]), fabsf(hi[k] - sv[k]));
-            far2 += fa * fa;
-        }
-        out[f] = d2 > r2 * (1.0f + kVsphereMargin);
-        in[f] = far2 < r2 * (1.0f - kVsphereMargin);
-    }
-    return (out[0] && out[1]) || (in[0] && in[1]);
-}
-
-// Walter et al.'s bound on the cosine between the normal n and the direction
-// from p to any point of the box [lo, hi], in the frame (t1, t2, n): the box's
-// extent along each frame axis is its centre's projection plus or minus the
-// half-extents projected by the axis' absolute components.
-__device__ inline float cos_bound(const float lo[3], const float hi[3], v3 p, v3 n, v3 t1, v3 t2, float hz) {
-    v3 c = {(lo[0] + hi[0]) * 0.5f - p.x, (lo[1] + hi[1]) * 0.5f - p.y, (lo[2] + hi[2]) * 0.5f - p.z};
-    v3 h = {(hi[0] - lo[0]) * 0.5f, (hi[1] - lo[1]) * 0.5f, (hi[2] - lo[2]) * 0.5f};
-    float cx = dot(t1, c), ex = fabsf(t1.x) * h.x + fabsf(t1.y) * h.y + fabsf(t1.z) * h.z;
-    float cy = dot(t2, c), ey = fabsf(t2.x) * h.x + fabsf(t2.y) * h.y + fabsf(t2.z) * h.z;
-    float zh = dot(n, c) + fabsf(n.x) * h.x + fabsf(n.y) * h.y + fabsf(n.z) * h.z;
-    float xl = cx - ex, xh = cx + ex, yl = cy - ey, yh = cy + ey;
-    float dx = (xl <= 0.0f && xh >= 0.0f) ? 0.0f : fminf(fabsf(xl), fabsf(xh));
-    float dy = (yl <= 0.0f && yh >= 0.0f) ? 0.0f : fminf(fabsf(yl), fabsf(yh));
-    float dxy2 = dx * dx + dy * dy;
-    if (zh <= hz) return 0.0f;
-    if (dxy2 == 0.0f) return 1.0f;
-    return zh / sqrtf(dxy2 + zh * zh);
-}
-
-struct TreeCtx {
-    const SceneView* s;
-    v3 p, n, cam;
-    int tri;
-    float hz, pad;
-    v3 t1, t2;     // tangent frame of n (Duff et al.)
-};
-
-__device__ inline TreeCtx tree_ctx(const SceneView* s, v3 p, v3 n, v3 cam, int tri, float hz, float pad) {
-    TreeCtx q{s, p, n, cam, tri, hz, pad, {0, 0, 0}, {0, 0, 0}};
-    onb(n, q.t1, q.t2);
-    return q;
-}
-
-__device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, int h2, const float* plo, const float* phi) {
-    if (ref == 0) return 0.0f;
-    if (ref < 0) {
-        int4 e = q.s->edges[~ref];
-        if (e.z == q.tri || e.w == q.tri) return 0.0f;
-    }
-    if (h2 && vsphere_prune(c, q.p - q.cam)) return 0.0f;
-    float b = cos_bound(c.lo, c.hi, q.p, q.n, q.t1, q.t2, q.hz);
-    if (b <= 0.0f) return 0.0f;
-    const float pv[3] = {q.p.x, q.p.y, q.p.z};
-    bool in = true;
-    for (int k = 0; k < 3; ++k)
-        if (pv[k] < plo[k] - q.pad || pv[k] > phi[k] + q.pad) in = false;
-    if (in) return 1.0f;
-    v3 ctr = {(c.lo[0] + c.hi[0]) * 0.5f, (c.lo[1] + c.hi[1]) * 0.5f, (c.lo[2] + c.hi[2]) * 0.5f};
-    return c.len * b / len(ctr - q.p);
-}
-
-template <class W>
-__device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rng& rk, float u_root, float& pdf, W& wk,
-                                  bool dbg = false) {
-    const ETNode* nodes = tv.nodes;
-    int node = 0;
-    float plo[3], phi[3];
-    {
-        const ETNode& r = nodes[0];
-        for (int k = 0; k < 3; ++k) { plo[k] = 3e38f; phi[k] = -3e38f; }
-        for (int c = 0; c < 2; ++c)
-            if (r.child[c] != 0)
-                for (int k = 0; k < 3; ++k) { plo[k] = fminf(plo[k], r.ch[c].lo[k]); phi[k] = fmaxf(phi[k], r.ch[c].hi[k]); }
-    }
-    pdf = 1.0f;
-    int level = -1;
-    float4 ub = make_float4(0, 0, 0, 0);
-    while (true) {
-        const ETNode& N = nodes[node];
-        wk.tree();
-        int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
-        float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
-        float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
-        float tot = w0 + w1;
-        if (!(tot > 0.0f)) return -1;
-        float u;
-        if (level < 0) u = u_root;
-        else {
-            if (level >= kMaxLevels) { atomicOr(q.s->err, kErrTreeDepth); return -1; }
-            if ((level & 3) == 0) ub = rk.block(1 + (level >> 2));
-            int c = level & 3;
-            u = c == 0 ? ub.x : (c == 1 ? ub.y : (c == 2 ? ub.z : ub.w));
-        }
-        float p0 = w0 / tot;
-        int side = u < p0 ? 0 : 1;
-        pdf *= side == 0 ? p0 : w1 / tot;
-        if (dbg) printf("  level %d node %d w0 %.9g w1 %.9g u %.9g side %d\n", level, node, w0, w1, u, side);
-        int ref = N.child[side];
-        if (ref < 0) return ~ref;
-        for (int k = 0; k < 3; ++k) { plo[k] = N.ch[side].lo[k]; phi[k] = N.ch[side].hi[k]; }
-        node = ref;
-        ++level;
-    }
-}
-
-// Probability that one descent ends at edge e: the product of the branch
-// probabilities along its leaf-to-root path (root choice included).
-template <class W>
-__device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int e, W& wk) {
-    int code = tv.eleaf[e];
-    if (code < 0) return 0.0f;
-    const ETNode* nodes = tv.nodes;
-    int node = code >> 1, side = code & 1;
-    float pdf = 1.0f;
-    for (int guard = 0; guard <= kMaxLevels + 1; ++guard) {
-        const ETNode& N = nodes[node];
-        wk.tree();
-        int pcode = node == 0 ? -1 : tv.enpar[node];
-        float plo[3], phi[3];
-        if (node == 0) {
-            for (int k = 0; k < 3; ++k) { plo[k] = 3e38f; phi[k] = -3e38f; }
-            for (int c = 0; c < 2; ++c)
-                if (N.child[c] != 0)
-                    for (int k = 0; k < 3; ++k) { plo[k] = fminf(plo[k], N.ch[c].lo[k]); phi[k] = fmaxf(phi[k], N.ch[c].hi[k]); }
-        } else {
-            const ETChild& pc = nodes[pcode >> 1].ch[pcode & 1];
-            for (int k = 0; k < 3; ++k) { plo[k] = pc.lo[k]; phi[k] = pc.hi[k]; }
-        }
-        int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
-        float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
-        float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
-        float tot = w0 + w1;
-        if (!(tot > 0.0f)) return 0.0f;
-        pdf *= (side == 0 ? w0 : w1) / tot;
-        if (node == 0) return pdf;
-        node = pcode >> 1;
-        side = pcode & 1;
-    }
-    atomicOr(q.s->err, kErrTreeDepth);
-    return 0.0f;
-}
-
-// ---------------------------------------------------------------------------
-// backward over paths: secondary edges at every vertex + interior adjoint
-// ---------------------------------------------------------------------------
-// PH: 0 = all in one pass; 1 = rebuild the path, sample the secondary edges and
-// queue their side-path queries; 2 = rebuild the path, read the side
-// radiances of its queries and run the adjoint sweep.
-// AOV (with MAXD = 1, PH = 0): gradient of the geometry-buffer channel a.aov;
-// only the first hit, no NEE, no secondary term.
-template <int MAXD, int STK, bool CNT, bool MIX, int PH = 0, bool AOV = false>
-__device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, const RenderArgs& a, const TreeView& tv,
-                                              const float* __restrict__ d_image, float* __restrict__ dV,
-                                              float* __restrict__ dA, float* __restrict__ camacc, const MixArgs& mx,
-                                              int mbase, int* stk, const SplitArgs& sp = SplitArgs{}) {
-    int lane = threadIdx.x;
-    int* my = stk + lane;
-    int m = mbase + lane;
-    CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    typename std::conditional<CNT, Work, NoWork>::type wk;
-    bool have0 = false;          // vertex-1 triangle gradients, scattered per wave group
-    int key0 = -1;
-    float g0[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (PH == 1 && m < a.M)
-#pragma unroll
-        for (int kk = 0; kk < MAXD; ++kk) sp.qidx[(size_t)kk * a.M + m] = -1;
-    const int depth = AOV ? 1 : a.depth;
-    if (m < a.M && (!a.mask || a.mask[m]) && depth >= 1 && a.ck_tri[m] >= 0) {
-        int pix, px, py;
-        uint32_t sid;
-        unit_pixel(k, a, m, pix, px, py, sid);
-        float W0 = PH == 1 ? 0.0f : d_image[pix] / (float)a.spp;
-        Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
-        float4 j = rc.block(0);
-        float sx = px + j.x, sy = py + j.y;
-        float ndx = 2.0f * sx / k.W - 1.0f, ndy = 1.0f - 2.0f * sy / k.H;
-        v3 d0 = k.f + k.r * (ndx * k.asp * k.th) + k.u * (ndy * k.th);
-        uint8_t vis = a.ck_vis[m];
-        // ---- rebuild the path's vertices
-        // per vertex: the ray reaching vertex k starts at vertex k-1 (camera for
-        // k = 0) along wc[k-1] (camera direction d0 for k = 0)
-        int tri[MAXD];
-        v3 xs[MAXD], ns[MAXD], wc[MAXD];
-        float sg[MAXD], rho[MAXD], beta[MAXD], cc[MAXD];
-        int nv = 0;
-        {
-            int t = a.ck_tri[m];
-            v3 o = k.c, d = d0;
-            v3 x = {a.ck_x[3 * (size_t)m], a.ck_x[3 * (size_t)m + 1], a.ck_x[3 * (size_t)m + 2]};
-            float b = 1.0f;
-#pragma unroll
-            for (int kk = 0; kk < MAXD; ++kk) {
-                if (kk >= depth) break;
-                TriGeom g = tri_geom(s, t);
-                float sgn = dot(d, cross(g.e1, g.e2)) < 0.0f ? 1.0f : -1.0f;
-                v3 n = shading_normal(s, t, g, x) * sgn;
-                float r = s.alb[t];
-                if (r == 0.0f && !AOV) break;
-                tri[kk] = t; xs[kk] = x; ns[kk] = n; sg[kk] = sgn; rho[kk] = r; beta[kk] = b;
-                cc[kk] = 0.0f;
-                wc[kk] = {0, 0, 0};
-                nv = kk + 1;
-                if (kk + 1 >= depth) break;
-                float4 ub = rc.block(2 * kk + 2);
-                v3 w = cosine_dir(n, ub.x, ub.y);
-                float c = dot(n, w);
-                if (c <= 0.0f) break;
-                int t2;
-                v3 x2;
-                if (kk + 1 < 3) {
-                    // vertices 1 and 2 were stored by the forward pass
-                    t2 = a.ck_tri[(size_t)(kk + 1) * a.M + m];
-                    if (t2 < 0) break;
-                    const float* cx = a.ck_x + 3 * ((size_t)(kk + 1) * a.M + m);
-                    x2 = {cx[0], cx[1], cx[2]};
-                } else if (PH == 2) {
-                    // the sampling pass traced this vertex: take its hit
-                    size_t slot = (size_t)(kk - 1) * a.M + m;
-                    t2 = sp.vtri[slot];
-                    if (t2 < 0) break;
-                    x2 = {sp.vx[3 * slot], sp.vx[3 * slot + 1], sp.vx[3 * slot + 2]};
-                } else {
-                    Hit h = trace_closest(s, x, w, s.tmin, 3.0e38f, my, BS, wk);
-                    if (PH == 1) {
-                        size_t slot = (size_t)(kk - 1) * a.M + m;
-                        sp.vtri[slot] = h.tri;
-                        if (h.tri >= 0) {
-                            v3 xh = hit_point(tri_geom(s, h.tri), x, w);
-                            sp.vx[3 * slot] = xh.x; sp.vx[3 * slot + 1] = xh.y; sp.vx[3 * slot + 2] = xh.z;
-                        }
-                    }
-                    if (h.tri < 0) break;
-                    t2 = h.tri;
-                    x2 = hit_point(tri_geom(s, t2), x, w);
-                }
-                if (s.alb[t2] == 0.0f) break;     // the next vertex would end the path before contributing
-                wc[kk] = w;
-                cc[kk] = c;
-                b *= r;
-                o = x; d = w; t = t2; x = x2;
-            }
-        }
-        v3 xbar[MAXD];
-#pragma unroll
-        for (int kk = 0; kk < MAXD; ++kk) xbar[kk] = {0, 0, 0};
-        // ---- secondary boundary term: one edge sample per vertex
-        if ((a.terms & DR_TERM_SECONDARY) && tv.valid && !AOV) {
-#pragma unroll
-            for (int kk = 0; kk < MAXD; ++kk) {
-                if (kk >= nv) break;
-                Rng rk{sid, a.view, kTagSedge + (uint32_t)(kk + 1), a.k0, a.k1};
-                float4 b0 = rk.block(0);
-                v3 p = xs[kk], n = ns[kk];
-                float pdf;
-                bool dbg = m == a.debug_unit;
-                int ei;
-                int qi = -1;
-                if (PH == 2) {
-                    qi = sp.qidx[(size_t)kk * a.M + m];
-                    if (qi < 0) continue;
-                    ei = sp.q[qi].edge;
-                    pdf = sp.q[qi].pdf;
-                } else if (MIX && mx.sec) {
-                    TreeCtx q = tree_ctx(&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag);
-                    // proposal mixture: component from the third uniform of the
-                    // block, proposal draw from the fourth
-                    float pt;
-                    if (b0.z < mx.mix) {
-                        ei = pick_cdf_d(mx.qcdf, s.E, (double)b0.w);
-                        pt = tree_pdf_edge(tv, q, ei, wk);
-                    } else {
-                        ei = tree_sample(tv, q, rk, b0.x, pt, wk, dbg);
-                        if (ei < 0) continue;
-                    }
-                    pdf = mx.mix * mx.q[ei] + (1.0f - mx.mix) * pt;
-                    if (!(pdf > 0.0f) || s.ekind[ei] == 0) continue;
-                } else {
-                    TreeCtx q = tree_ctx(&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag);
-                    ei = tree_sample(tv, q, rk, b0.x, pdf, wk, dbg);
-                }
-                if (ei < 0) continue;
-                int4 e = s.edges[ei];
-                if (PH != 2) {
-                    if (e.z == tri[kk] || e.w == tri[kk]) continue;
-                    if (s.ekind[ei] == 2 && !silhouette_from(s, e, p)) continue;
-                }
-                v3 pa = ld3(s.P, e.x), pb = ld3(s.P, e.y);
-                v3 w = pa + (pb - pa) * b0.y - p;
-                if (PH != 2 && dot(n, w) <= kHorizon * s.diag) continue;
-                v3 v0p = pa - p, v1p = pb - p;
-                v3 c = cross(v0p, v1p);
-                float cn = len(c);
-                if (PH != 2 && cn == 0.0f) continue;
-                v3 nh = c * (1.0f / cn);
-                float wl = len(w);
-                v3 wh = w * (1.0f / wl);
-                v3 wp = nrm(wh + nh * kEps3), wm = nrm(wh - nh * kEps3);
-                int rem = a.depth - (kk + 1);
-                float Lp, Lm;
-                if (PH == 1) {
-                    // queue the side paths: one atomic per wave
-                    unsigned long long bal = __ballot(1);
-                    int leader = __ffsll(bal) - 1;
-                    int base = 0;
-                    // one queue segment of a.M slots per path vertex, so that
-                    // the side paths of a segment all have the same length
-                    if (lane == leader) base = atomicAdd(&sp.count[kk], __popcll(bal));
-                    base = __shfl(base, leader, BS);
-                    int slot = kk * a.M + base + __popcll(bal & ((1ull << lane) - 1ull));
-                    SideQuery Q;
-                    Q.p[0] = p.x; Q.p[1] = p.y; Q.p[2] = p.z;
-                    Q.wp[0] = wp.x; Q.wp[1] = wp.y; Q.wp[2] = wp.z;
-                    Q.wm[0] = wm.x; Q.wm[1] = wm.y; Q.wm[2] = wm.z;
-                    Q.sid = sid;
-                    Q.edge = ei;
-                    Q.pdf = pdf;
-                    Q.k = kk;
-                    sp.q[slot] = Q;
-                    sp.qidx[(size_t)kk * a.M + m] = slot;
-                    continue;
-                } else if (PH == 2) {
-                    float2 L = sp.res[qi];
-                    Lp = L.x;
-                    Lm = L.y;
-                } else {
-                    radiance_pair(s, rk, kSideBlockBase, p, wp, wm, s.tmin, false, rem, my, BS, wk, Lp, Lm);
-                }
-                // the cosine is continuous across the edge; only the radiance jumps
-                float cosw = dot(n, wh);
-                float Fp = rho[kk] / kPi * cosw * Lp;
-                float Fm = rho[kk] / kPi * cosw * Lm;
-                if (Fp == Fm) continue;
-                float Wk = d_image[pix] * beta[kk] / (float)a.spp;
-                float wgt = Wk * (Fp - Fm) * len(cross(pb - pa, wh)) / (cn * wl * pdf);
-                if (dbg)
-                    printf("unit %d vertex %d tri %d p=(%.9g %.9g %.9g) n=(%.9g %.9g %.9g) edge %d pdf %.9g t %.9g Lp %.9g "
-                           "Lm %.9g cos %.9g W %.9g wgt %.9g\n",
-                           m, kk + 1, tri[kk], p.x, p.y, p.z, n.x, n.y, n.z, ei, pdf, b0.y, Lp, Lm, cosw, Wk, wgt);
-                atomic_add3(dV, e.x, cross(v1p, wh) * wgt);
-                atomic_add3(dV, e.y, cross(wh, v0p) * wgt);
-                wk.atomics(6);
-                if (MIX && mx.estats) {
-                    v3 c0 = cross(v1p, wh), c1 = cross(wh, v0p);
-                    atomicAdd(&mx.estats[ei], pdf * wgt * wgt * (dot(c0, c0) + dot(c1, c1)));
-                }
-                xbar[kk] += (cross(wh, v1p) + cross(v0p, wh)) * wgt;
-            }
-        }
-        // ---- reverse sweep: interior term and propagation of vertex adjoints
-        if (PH == 1) nv = 0;
-        bool interior = (a.terms & DR_TERM_INTERIOR) != 0;
-        float Aft = 0.0f;          // radiance from later vertices per unit throughput there
-        v3 carry = {0, 0, 0};      // adjoint of this vertex's position from the next ray-plane
-        v3 gd0 = {0, 0, 0};
-        float grho_k = 0.0f;       // albedo adjoint of vertices 2.. (scattered with their vertices)
-#pragma unroll
-        for (int kk = MAXD - 1; kk >= 0; --kk) {
-            if (kk >= nv) continue;
-            int t = tri[kk];
-            TriGeom g = tri_geom(s, t);
-            v3 gns = {0, 0, 0};
-            v3 gx = xbar[kk] + carry;
-            float Nk = 0.0f;
-            bool cont = false;
-            float Ab = 0.0f;
-            if (AOV) {
-                // d(buffer)/d(position, oriented normal, albedo) at the first hit;
-                // with all channels (aov = 8) their loss gradients are npix apart
-                if (interior) {
-                    float wc7[7];
-                    long npix = (long)a.Ww * (k.y1 - k.y0);
-#pragma unroll
-                    for (int c = 0; c < 7; ++c)
-                        wc7[c] = a.aov == 8 ? d_image[c * npix + pix] / (float)a.spp : (a.aov == c + 1 ? W0 : 0.0f);
-                    gx += v3{wc7[0], wc7[1], wc7[2]};
-                    gns = v3{wc7[3], wc7[4], wc7[5]};
-                    g0[9] = wc7[6];
-                }
-            } else {
-            // NEE of this vertex, recomputed from its random numbers; the
-            // visibility comes from the forward pass
-            NeeSample q = nee_sample(s, rc.block(2 * kk + 1), xs[kk], ns[kk]);
-            float Kk = ((vis >> kk) & 1) ? q.K : 0.0f;
-            float nee_cos = dot(ns[kk], q.w);
-            Nk = rho[kk] * nee_cos * Kk;
-            cont = cc[kk] > 0.0f;
-            Ab = cont ? Aft : 0.0f;
-            if (interior) {
-                float gN = W0 * beta[kk];
-                float gw = cont ? W0 * beta[kk] * Ab : 0.0f;
-                float grho = gN * nee_cos * Kk + gw;
-                if (kk == 0) g0[9] = grho;
-                else grho_k = grho;
-                gns = q.w * (gN * rho[kk] * Kk);
-                if (cont) gns += wc[kk] * (gw * rho[kk] / cc[kk]);
-            }
-            }
-            v3 gp0 = {0, 0, 0}, gp1 = {0, 0, 0}, gp2 = {0, 0, 0};
-            if (gns.x != 0.0f || gns.y != 0.0f || gns.z != 0.0f)
-                shading_normal_adj(s, t, g, xs[kk], gns * sg[kk], gx, gp0, gp1, gp2);
-            v3 go = {0, 0, 0}, gd = {0, 0, 0};
-            v3 org = kk == 0 ? k.c : xs[kk == 0 ? 0 : kk - 1];
-            v3 dir = kk == 0 ? d0 : wc[kk == 0 ? 0 : kk - 1];
-            ray_plane_adj(g, org, dir, gx, go, gd, gp0, gp1, gp2);
-            if (kk == 0) {
-                have0 = true;
-                key0 = t;
-                g0[0] = gp0.x; g0[1] = gp0.y; g0[2] = gp0.z;
-                g0[3] = gp1.x; g0[4] = gp1.y; g0[5] = gp1.z;
-                g0[6] = gp2.x; g0[7] = gp2.y; g0[8] = gp2.z;
-            } else if (__ballot(1) == ~0ull) {
-                // every lane of the wave is at this vertex: lanes that hit the
-                // same triangle (large walls, say) are summed before the atomics
-                const float gv[10] = {gp0.x, gp0.y, gp0.z, gp1.x, gp1.y, gp1.z, gp2.x, gp2.y, gp2.z, grho_k};
-                scatter_grouped(true, t, gv, 4, [&](int tt, int i) {
-                    return i == 9 ? &dA[tt] : &dV[3 * s.I[3 * tt + i / 3] + (i % 3)];
-                });
-                grho_k = 0.0f;
-            } else {
-                int i0 = s.I[3 * t], i1 = s.I[3 * t + 1], i2 = s.I[3 * t + 2];
-                atomic_add3(dV, i0, gp0);
-                atomic_add3(dV, i1, gp1);
-                atomic_add3(dV, i2, gp2);
-                if (grho_k != 0.0f) atomicAdd(&dA[t], grho_k);
-                grho_k = 0.0f;
-            }
-            wk.atomics(10);
-            if (kk == 0) {
-                ca.c += go;
-                gd0 = gd;
-            } else {
-                carry = go;        // the ray of vertex kk starts at vertex kk-1; its direction is held fixed
-            }
-            Aft = Nk + (cont ? rho[kk] * Ab : 0.0f);
-        }
-        // camera ray direction d = f + a r + b u
-        ca.f += gd0;
-        ca.r += gd0 * (ndx * k.asp * k.th);
-        ca.u += gd0 * (ndy * k.th);
-    }
-    scatter_grouped(have0, key0, g0, 4, [&](int t, int i) {
-        return i == 9 ? &dA[t] : &dV[3 * s.I[3 * t + i / 3] + (i % 3)];
-    });
-    flush_work(wk, a.counters);
-    flush_cam(ca, camacc);
-}
-
-// dL/d(position, look_at, up) from the frame adjoints (f, r, u, c).
-template <int MAXD, int STK, bool CNT, bool MIX, bool AOV = false>
-__global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs a, TreeView tv, const float* __restrict__ d_image,
-                                                 float* __restrict__ dV, float* __restrict__ dA, float* __restrict__ camacc,
-                                                 MixArgs mx) {
-    __shared__ int stk[STK * BS];
-    int sh = blockIdx.x & (a.gshards - 1);
-    backward_body<MAXD, STK, CNT, MIX, 0, AOV>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride, camacc + 12 * sh,
-                                       mx, blockIdx.x * BS, stk);
-}
-
-// Split backward, pass 1: secondary edge samples of every path vertex, their
-// side-path queries appended to a compact queue.
-template <int MAXD, int STK>
-__global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp) {
-    __shared__ int stk[STK * BS];
-    MixArgs mx{};
-    backward_body<MAXD, STK, false, false, 1>(s, k, a, tv, nullptr, nullptr, nullptr, nullptr, mx, blockIdx.x * BS, stk, sp);
-}
-
-// Split backward, pass 2: both one-sided radiances of every queued query, one
-// query per lane (no idle lanes), with the query's own Philox stream.
-template <int STK>
-__global__ __launch_bounds__(BS) void k_side(SceneView s, RenderArgs a, SplitArgs sp, int kk) {
-    __shared__ int stk[STK * BS];
-    int lane = threadIdx.x;
-    int* my = stk + lane;
-    NoWork wk;
-    int n = sp.count[kk];
-    for (int base = blockIdx.x * BS; base < n; base += gridDim.x * BS) {
-        int i = kk * a.M + base + lane;
-        if (base + lane < n) {
-            SideQuery Q = sp.q[i];
-            Rng rk{Q.sid, a.view, kTagSedge + (uint32_t)(Q.k + 1), a.k0, a.k1};
-            int rem = a.depth - (Q.k + 1);
-            v3 p = {Q.p[0], Q.p[1], Q.p[2]};
-            v3 wp = {Q.wp[0], Q.wp[1], Q.wp[2]}, wm = {Q.wm[0], Q.wm[1], Q.wm[2]};
-            float Lp, Lm;
-            radiance_pair(s, rk, kSideBlockBase, p, wp, wm, s.tmin, false, rem, my, BS, wk, Lp, Lm);
-            sp.res[i] = make_float2(Lp, Lm);
-        }
-    }
-}
-
-// Split backward, pass 3: boundary contributions from the queued radiances and
-// the adjoint sweep.
-template <int MAXD, int STK>
-__global__ __launch_bounds__(BS) void k_bwd_adjoint(SceneView s, Cam k, RenderArgs a, TreeView tv,
-                                                    const float* __restrict__ d_image, float* __restrict__ dV,
-                                                    float* __restrict__ dA, float* __restrict__ camacc, SplitArgs sp) {
-    __shared__ int stk[STK * BS];
-    int sh = blockIdx.x & (a.gshards - 1);
-    MixArgs mx{};
-    backward_body<MAXD, STK, false, false, 2>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride,
-                                              camacc + 12 * sh, mx, blockIdx.x * BS, stk, sp);
-}
-
-__device__ inline void cam_finalize(const Cam& k, const float* __restrict__ acc, float* __restrict__ d_camera) {
-    v3 gf = {acc[0], acc[1], acc[2]}, gr = {acc[3], acc[4], acc[5]}, gu = {acc[6], acc[7], acc[8]}, gc = {acc[9], acc[10], acc[11]};
-    v3 look = k.look, up = k.upv;
-    // u = r x f
-    gr += cross(k.f, gu);
-    gf += cross(gu, k.r);
-    // r = normalize(f x up)
-    v3 gg = nrm_adj(cross(k.f, up), gr);
-    gf += cross(up, gg);
-    v3 gup = cross(gg, k.f);
-    // f = normalize(look - c)
-    v3 gh = nrm_adj(look - k.c, gf);
-    v3 gl = gh;
-    gc -= gh;
-    d_camera[0] = gc.x; d_camera[1] = gc.y; d_camera[2] = gc.z;
-    d_camera[3] = gl.x; d_camera[4] = gl.y; d_camera[5] = gl.z;
-    d_camera[6] = gup.x; d_camera[7] = gup.y; d_camera[8] = gup.z;
-}
-
-__global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, int shards, float* __restrict__ d_camera) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float sum[12];
-    for (int i = 0; i < 12; ++i) {
-        sum[i] = 0.0f;
-        for (int h = 0; h < shards; ++h) sum[i] += acc[12 * h + i];
-    }
-    cam_finalize(k, sum, d_camera);
-}
-
-// out[i] = sum over the copies of shard[h * stride + i], i < n
-__global__ void k_reduce_shards(const float* __restrict__ shard, int shards, long stride, long n, float* __restrict__ out) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float v = 0.0f;
-    for (int h = 0; h < shards; ++h) v += shard[h * stride + i];
-    out[i] = v;
-}
-
-// ---------------------------------------------------------------------------
-// batches of views: one launch per kernel for every view. Each block of 64
-// units lies in one view, so the view's arguments are uniform per block.
-// Work items of `chunk` blocks are taken in grid order, or from an atomic
-// counter when the grid is persistent (smaller than the work list).
-// ---------------------------------------------------------------------------
-__device__ inline int batch_view(const BatchLaunch& L, int b) {
-    int lo = 0, hi = L.nviews - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (L.boff[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ inline int batch_next(const BatchLaunch& L, int it, int* slot) {
-    int item;
-    if (L.queue) {
-        if (threadIdx.x == 0) *slot = atomicAdd(L.queue, 1);
-        __syncthreads();
-        item = *slot;
-        __syncthreads();
-    } else {
-        item = blockIdx.x + it * gridDim.x;
-    }
-    return __builtin_amdgcn_readfirstlane(item);
-}
-
-template <int STK>
-__global__ __launch_bounds__(BS) void k_forward_batch(SceneView s, BatchLaunch L) {
-    __shared__ int stk[STK * BS];
-    __shared__ int slot;
-    for (int it = 0;; ++it) {
-        int item = batch_next(L, it, &slot);
-        if (item >= (L.total + L.chunk - 1) / L.chunk) break;
-        for (int c = 0; c < L.chunk; ++c) {
-            int b = item * L.chunk + c;
-            if (b >= L.total) break;
-            int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
-            const BatchView& bv = L.views[v];
-            forward_body<STK, false>(s, bv.k, bv.a, bv.image, bv.reduce, (b - L.boff[v]) * BS, stk);
-        }
-    }
-}
-
-template <int STK>
-__global__ __launch_bounds__(BS) void k_primary_batch(SceneView s, BatchLaunch L, float* __restrict__ dV) {
-    __shared__ int stk[STK * BS];
-    __shared__ int slot;
-    MixArgs mx{};
-    for (int it = 0;; ++it) {
-        int item = batch_next(L, it, &slot);
-        if (item >= (L.total + L.chunk - 1) / L.chunk) break;
-        for (int c = 0; c < L.chunk; ++c) {
-            int b = item * L.chunk + c;
-            if (b >= L.total) break;
-            int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
-            const BatchView& bv = L.views[v];
-            int sh = blockIdx.x & (L.gshards - 1);
-            primary_body<STK, false, false>(s, bv.k, bv.a, bv.pe, bv.pcdf, bv.d_image, dV + sh * L.gstride,
-                                            bv.camacc + 12 * sh, mx, (b - L.boff[v]) * BS, stk);
-        }
-    }
-}
-
-template <int MAXD, int STK>
-__global__ __launch_bounds__(BS) void k_backward_batch(SceneView s, BatchLaunch L, float* __restrict__ dV,
-                                                       float* __restrict__ dA) {
-    __shared__ int stk[STK * BS];
-    __shared__ int slot;
-    MixArgs mx{};
-    for (int it = 0;; ++it) {
-        int item = batch_next(L, it, &slot);
-        if (item >= (L.total + L.chunk - 1) / L.chunk) break;
-        for (int c = 0; c < L.chunk; ++c) {
-            int b = item * L.chunk + c;
-            if (b >= L.total) break;
-            int v = __builtin_amdgcn_readfirstlane(batch_view(L, b));
-            const BatchView& bv = L.views[v];
-            int sh = blockIdx.x & (L.gshards - 1);
-            backward_body<MAXD, STK, false, false>(s, bv.k, bv.a, bv.tv, bv.d_image, dV + sh * L.gstride,
-                                                   dA + sh * L.gstride, bv.camacc + 12 * sh, mx, (b - L.boff[v]) * BS,
-                                                   stk);
-        }
-    }
-}
-
-__global__ void k_cam_finalize_batch(const BatchView* __restrict__ views, int n, int shards, float* __restrict__ d_cameras) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    float sum[12];
-    for (int i = 0; i < 12; ++i) {
-        sum[i] = 0.0f;
-        for (int h = 0; h < shards; ++h) sum[i] += views[v].camacc[12 * h + i];
-    }
-    cam_finalize(views[v].k, sum, d_cameras + 9 * v);
-}
-
-__global__ void k_batch_zero(const BatchView* __restrict__ views, int n, int image, int shards) {
-    // zeroes each view's image (image = 1) or camera accumulator (image = 0)
-    int v = blockIdx.y;
-    if (v >= n) return;
-    const BatchView& bv = views[v];
-    if (image) {
-        int npix = bv.a.M / bv.a.spp;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += gridDim.x * blockDim.x) bv.image[i] = 0.0f;
-    } else if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < 12 * shards; i += blockDim.x) bv.camacc[i] = 0.0f;
-    }
-}
-
-__global__ void k_batch_seed(BatchView* __restrict__ views, int n, uint32_t add) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) views[v].a.k0 += add;
-}
-
-__global__ void k_fill_i32(int* __restrict__ p, int v) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
-}
-
-__global__ void k_fill_count(int* __restrict__ c, int n) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = 0;
-}
-
-__global__ void k_fill(float* __restrict__ p, long n, float v) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-// ---------------------------------------------------------------------------
-// host launchers
-// ---------------------------------------------------------------------------
-static inline int nblk(long n, int bs) { return (int)((n + bs - 1) / bs); }
-
-// Brackets one kernel launch with HIP events when profiling is on.
-struct EvScope {
-    drScene_t* s;
-    int kind;
-    hipStream_t st;
-    hipEvent_t a = nullptr, b = nullptr;
-    EvScope(drScene_t* s_, int kind_, hipStream_t st_) : s(s_), kind(kind_), st(st_) {
-        s->launches[kind]++;
-        if (!s->prof_events) return;
-        (void)hipEventCreate(&a);
-        (void)hipEventCreate(&b);
-        (void)hipEventRecord(a, st);
-    }
-    ~EvScope() {
-        if (!a) return;
-        (void)hipEventRecord(b, st);
-        s->evs.push_back({a, b, kind});
-    }
-};
-
-static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions& o) {
-    RenderArgs a;
-    a.spp = o.spp;
-    a.depth = o.max_depth;
-    a.Ww = cam.x1 - cam.x0;
-    a.M = a.Ww * (cam.y1 - cam.y0) * o.spp;
-    a.k0 = (uint32_t)(o.seed & 0xffffffffu);
-    a.k1 = (uint32_t)(o.seed >> 32);
-    a.view = o.view_id;
-    a.terms = o.terms ? o.terms : DR_TERM_ALL;
-    a.mask = o.unit_mask;
-    const char* du = std::getenv("DIFFRT_DEBUG_UNIT");
-    a.debug_unit = du ? std::atoi(du) : -1;
-    a.counters = s->prof_counters ? s->counters.as<unsigned long long>() : nullptr;
-    a.ck_tri = s->ck_tri.as<int>();
-    a.ck_x = s->ck_x.as<float>();
-    a.ck_vis = s->ck_vis.as<uint8_t>();
-    a.gshards = 1;
-    a.gstride = 0;
-    a.aov = o.aov;
-    return a;
-}
-
-// Traversal stack per lane: 32 entries when the BVH is at most 32 internal
-// nodes deep (then the stack can never overflow), 64 otherwise.
-static inline bool small_stack(const drScene_t* s) { return s->bvh_depth <= 32; }
-
-drStatus launch_forward(drScene_t* s, const Cam& cam, const drRenderOptions& o, float* image, hipStream_t st) {
-    RenderArgs a = make_args(s, cam, o);
-    SceneView sv = s->view();
-    bool sm = small_stack(s);
-    sv.stk_cap = sm ? 32 : kStackDepth;
-    bool reduce = (BS % o.spp) == 0;
-    long npix = (long)a.Ww * (cam.y1 - cam.y0) * (o.aov == 8 ? 7 : 1);
-    if (!reduce) k_fill<<<nblk(npix, 256), 256, 0, st>>>(image, npix, 0.0f);
-    {
-        EvScope ev(s, 0, st);
-        dim3 g(nblk(a.M, BS)), b(BS);
-        int red = reduce ? 1 : 0;
-        if (o.aov) {
-            if (sm) k_forward_aov<32><<<g, b, 0, st>>>(sv, cam, a, image, red);
-            else k_forward_aov<kStackDepth><<<g, b, 0, st>>>(sv, cam, a, image, red);
-        } else if (a.counters) {
-            if (sm) k_forward<32, true><<<g, b, 0, st>>>(sv, cam, a, image, red);
-            else k_forward<kStackDepth, true><<<g, b, 0, st>>>(sv, cam, a, image, red);
-        } else {
-            if (sm) k_forward<32, false><<<g, b, 0, st>>>(sv, cam, a, image, red);
-            else k_forward<kStackDepth, false><<<g, b, 0, st>>>(sv, cam, a, image, red);
-        }
-    }
-    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
-}
 
 drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o, const float* d_image, float* d_vertices,
                          float* d_albedo, float* d_camera, hipStream_t st) {
@@ -1260,24 +49,22 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
     if ((terms & DR_TERM_PRIMARY) && s->E > 0) {
         EvScope ev(s, 1, st);
         a.counters = cbase ? cbase + 8 : nullptr;
-        dim3 g(nblk(a.M, BS)), b(BS);
+        dim3 g(nblk(a.M, BS));
         const PEdge* pe = s->pe.as<PEdge>();
         const double* pc = s->pcdf.as<double>();
-#define DR_PRIM(S, C, X) k_primary<S, C, X><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx)
-        if (o.aov) {
-            if (sm) k_primary<32, false, false, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx);
-            else k_primary<kStackDepth, false, false, true><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx);
-        } else if (use_mix) {
-            if (sm) DR_PRIM(32, false, true);
-            else DR_PRIM(kStackDepth, false, true);
-        } else if (a.counters) {
-            if (sm) DR_PRIM(32, true, false);
-            else DR_PRIM(kStackDepth, true, false);
-        } else {
-            if (sm) DR_PRIM(32, false, false);
-            else DR_PRIM(kStackDepth, false, false);
+Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
+        // production variant: edge samples, then a compact queue of those
+        // whose two sides hit different triangles, traced densely
+        int3* pq = nullptr;
+        int* pcount = nullptr;
+        if (s->split_primary && !v.aov && !v.mix && !v.counters) {
+            if (s->pq.ensure(sizeof(int3) * (size_t)a.M) != hipSuccess || s->pcount.ensure(sizeof(int) * 64) != hipSuccess)
+                return DR_ERROR_OUT_OF_MEMORY;
+            pq = s->pq.as<int3>();
+            pcount = s->pcount.as<int>();
         }
-#undef DR_PRIM
+        int paths_grid = std::max(1, std::min(nblk((long)a.M, BS), 256 * 16));
+        launch_primary_kernel(v, g, sv, cam, a, pe, pc, d_image, dV, camacc, mx, pq, pcount, paths_grid, st);
     }
     if (o.aov) {
         // geometry buffer: interior term at the first hit only
@@ -1298,7 +85,7 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
         tv.enpar = s->enpar.as<int>();
         EvScope ev(s, 2, st);
         a.counters = cbase ? cbase + 16 : nullptr;
-        dim3 g(nblk(a.M, BS)), b(BS);
+        dim3 g(nblk(a.M, BS));
         bool split = !use_mix && !a.counters && s->split_backward;
         SplitArgs sp{};
         // queue capacity: MAXD (the kernels' template depth: 1, 3 or 6) slots per unit
@@ -1320,104 +107,23 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
             k_fill_count<<<1, 64, 0, st>>>(sp.count, maxd);
         }
         int side_grid = std::max(1, std::min(nblk((long)a.M, BS), 256 * 16));
-#define DR_SPLIT(D, S)                                                                                     \
-    k_bwd_sample<D, S><<<g, b, 0, st>>>(sv, cam, a, tv, sp);                                               \
-    for (int kq = 0; kq < std::min(o.max_depth, D); ++kq) k_side<S><<<side_grid, b, 0, st>>>(sv, a, sp, kq);     \
-    k_bwd_adjoint<D, S><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, sp);
-#define DR_BWD(D, S, C, X) k_backward<D, S, C, X><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx)
-#define DR_BWD_D(D)                                   \
-    if (split) {                                      \
-        if (sm) { DR_SPLIT(D, 32) }                   \
-        else { DR_SPLIT(D, kStackDepth) }             \
-    } else if (use_mix) {                             \
-        if (sm) DR_BWD(D, 32, false, true);           \
-        else DR_BWD(D, kStackDepth, false, true);     \
-    } else if (a.counters) {                          \
-        if (sm) DR_BWD(D, 32, true, false);           \
-        else DR_BWD(D, kStackDepth, true, false);     \
-    } else {                                          \
-        if (sm) DR_BWD(D, 32, false, false);          \
-        else DR_BWD(D, kStackDepth, false, false);    \
-    }
+PathLaunch pl{Variant{false, use_mix, a.counters != nullptr, sm}, split, g, side_grid, o.max_depth, sv, cam, a,
+                      tv, sp, d_image, dV, dA, camacc, mx};
         if (o.max_depth <= 1) {
-            DR_BWD_D(1)
+            if (sm) launch_paths_stack<1, 32>(pl, st);
+            else launch_paths_stack<1, kStackDepth>(pl, st);
         } else if (o.max_depth <= 3) {
-            DR_BWD_D(3)
+            if (sm) launch_paths_stack<3, 32>(pl, st);
+            else launch_paths_stack<3, kStackDepth>(pl, st);
         } else {
-            DR_BWD_D(6)
+            if (sm) launch_paths_stack<6, 32>(pl, st);
+            else launch_paths_stack<6, kStackDepth>(pl, st);
         }
-#undef DR_BWD_D
-#undef DR_BWD
-#undef DR_SPLIT
     }
     if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, shards, stride, 3L * s->V, d_vertices);
     if (d_albedo) k_reduce_shards<<<nblk(s->T, 256), 256, 0, st>>>(dA, shards, stride, s->T, d_albedo);
     if (d_camera)
         k_cam_finalize<<<1, 1, 0, st>>>(cam, camacc, shards, d_camera);
-    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
-}
-
-static int batch_grid(const BatchLaunch& L, int ctas) {
-    int items = (L.total + L.chunk - 1) / L.chunk;
-    return ctas > 0 ? std::max(1, std::min(ctas, items)) : std::max(1, items);
-}
-
-drStatus launch_batch_forward(drScene_t* s, BatchLaunch L, int ctas, int max_pixels, hipStream_t st) {
-    SceneView sv = s->view();
-    bool sm = small_stack(s);
-    sv.stk_cap = sm ? 32 : kStackDepth;
-    dim3 zg(std::max(1, std::min((max_pixels + 255) / 256, 1024)), L.nviews);
-    k_batch_zero<<<zg, 256, 0, st>>>(L.views, L.nviews, 1, L.gshards);
-    if (L.total == 0) return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
-    if (!(ctas > 0)) L.queue = nullptr;
-    else k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
-    int grid = batch_grid(L, ctas);
-    if (sm) k_forward_batch<32><<<grid, BS, 0, st>>>(sv, L);
-    else k_forward_batch<kStackDepth><<<grid, BS, 0, st>>>(sv, L);
-    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
-}
-
-drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth, float* shard, float* d_vertices,
-                               float* d_albedo, float* d_cameras, hipStream_t st) {
-    SceneView sv = s->view();
-    bool sm = small_stack(s);
-    sv.stk_cap = sm ? 32 : kStackDepth;
-    // `shard`: gshards copies of [dV (3V) | dA (T)], gstride = 3V + T floats apart
-    float* dV = shard;
-    float* dA = shard + 3L * s->V;
-    k_fill<<<nblk((long)L.gshards * L.gstride, 256), 256, 0, st>>>(shard, (long)L.gshards * L.gstride, 0.0f);
-    k_batch_zero<<<dim3(1, L.nviews), 64, 0, st>>>(L.views, L.nviews, 0, L.gshards);
-    if (L.total > 0) {
-        if (!(ctas > 0)) L.queue = nullptr;
-        int grid = batch_grid(L, ctas);
-        if (s->E > 0) {
-            if (L.queue) k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
-            if (sm) k_primary_batch<32><<<grid, BS, 0, st>>>(sv, L, dV);
-            else k_primary_batch<kStackDepth><<<grid, BS, 0, st>>>(sv, L, dV);
-        }
-        if (depth >= 1) {
-            if (L.queue) k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
-#define DR_BB(D)                                                                  \
-    if (sm) k_backward_batch<D, 32><<<grid, BS, 0, st>>>(sv, L, dV, dA);          \
-    else k_backward_batch<D, kStackDepth><<<grid, BS, 0, st>>>(sv, L, dV, dA);
-            if (depth <= 1) {
-                DR_BB(1)
-            } else if (depth <= 3) {
-                DR_BB(3)
-            } else {
-                DR_BB(6)
-            }
-#undef DR_BB
-        }
-    }
-    if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, L.gshards, L.gstride, 3L * s->V, d_vertices);
-    if (d_albedo) k_reduce_shards<<<nblk(s->T, 256), 256, 0, st>>>(dA, L.gshards, L.gstride, s->T, d_albedo);
-    if (d_cameras) k_cam_finalize_batch<<<(L.nviews + 63) / 64, 64, 0, st>>>(L.views, L.nviews, L.gshards, d_cameras);
-    return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
-}
-
-drStatus launch_batch_seed(BatchView* views, int n, uint32_t add, hipStream_t st) {
-    k_batch_seed<<<(n + 63) / 64, 64, 0, st>>>(views, n, add);
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 

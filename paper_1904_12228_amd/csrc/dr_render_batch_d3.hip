@@ -1,0 +1,6 @@
+// Batched path backward kernels at kernel depth 3.
+#include "dr_paths_impl.h"
+
+namespace dr {
+template void launch_batch_paths<3>(bool, int, const SceneView&, const BatchLaunch&, float*, float*, hipStream_t);
+}  // namespace dr

@@ -1,0 +1,6 @@
+// Path backward kernels at kernel depth 3, full-size traversal stack.
+#include "dr_paths_impl.h"
+
+namespace dr {
+template void launch_paths_stack<3, kStackDepth>(const PathLaunch&, hipStream_t);
+}  // namespace dr

@@ -1,0 +1,39 @@
+// Primary edge samples (k_primary): every variant.
+#include "dr_kernels.h"
+#include "dr_launch.h"
+
+namespace dr {
+
+void launch_primary_kernel(const Variant& v, dim3 g, const SceneView& sv, const Cam& cam, const RenderArgs& a,
+                           const PEdge* pe, const double* pc, const float* d_image, float* dV, float* camacc,
+                           const MixArgs& mx, int3* pq, int* pcount, int paths_grid, hipStream_t st) {
+    dim3 b(BS);
+    if (pq && !v.aov && !v.mix && !v.counters) {
+        k_fill_count<<<1, 64, 0, st>>>(pcount, 1);
+        if (v.small) {
+            k_prim_sample<32><<<g, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount);
+            k_prim_paths<32><<<paths_grid, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, d_image, dV, camacc);
+        } else {
+            k_prim_sample<kStackDepth><<<g, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount);
+            k_prim_paths<kStackDepth><<<paths_grid, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, d_image, dV, camacc);
+        }
+        return;
+    }
+#define DR_PRIM(S, C, X, A) k_primary<S, C, X, A><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx)
+    if (v.aov) {
+        if (v.small) DR_PRIM(32, false, false, true);
+        else DR_PRIM(kStackDepth, false, false, true);
+    } else if (v.mix) {
+        if (v.small) DR_PRIM(32, false, true, false);
+        else DR_PRIM(kStackDepth, false, true, false);
+    } else if (v.counters) {
+        if (v.small) DR_PRIM(32, true, false, false);
+        else DR_PRIM(kStackDepth, true, false, false);
+    } else {
+        if (v.small) DR_PRIM(32, false, false, false);
+        else DR_PRIM(kStackDepth, false, false, false);
+    }
+#undef DR_PRIM
+}
+
+}  // namespace dr

@@ -138,7 +138,7 @@ class EdgeProposal:
 
 
 def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mix=0.0, mix_terms=0,
-                           d_image=1.0, terms=0):
+                           d_image=1.0, terms=0, edge_t=0):
     """Sum over vertex-gradient entries of the variance of the estimate across
     seeds, the mean gradient, and the mean time of one drRenderBackward (HIP
     events around the call, forward checkpoints excluded)."""
@@ -155,7 +155,7 @@ def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=No
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         scene.render_backward(cam, spp, depth, dimg, seed=sd, terms=terms, want=("vertices",), outs=(dv, None, None),
-                              edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms)
+                              edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t)
         e1.record(st)
         e1.synchronize()
         ms += e0.elapsed_time(e1)
@@ -168,9 +168,112 @@ def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=No
     return float(var.clamp(min=0).sum()), mean, ms / n
 
 
+def gradient_samples(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mix=0.0, mix_terms=0, d_image=1.0,
+                     terms=0, edge_t=0):
+    """Per-seed vertex gradients [len(seeds), 3V] (float64, device) and the
+    drRenderBackward duration of each seed in ms (HIP events around the call,
+    forward checkpoints excluded)."""
+    dev = scene.device
+    x0, y0, x1, y1 = cam.win()
+    dimg = torch.full((y1 - y0, x1 - x0), float(d_image), dtype=torch.float32, device=dev)
+    dv = torch.empty((scene.num_vertices, 3), dtype=torch.float32, device=dev)
+    out = torch.empty((len(seeds), 3 * scene.num_vertices), dtype=torch.float64, device=dev)
+    ms = []
+    st = torch.cuda.current_stream()
+    for i, sd in enumerate(seeds):
+        scene.render(cam, spp, depth, seed=sd)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        scene.render_backward(cam, spp, depth, dimg, seed=sd, terms=terms, want=("vertices",), outs=(dv, None, None),
+                              edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t)
+        e1.record(st)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        out[i] = dv.reshape(-1).double()
+    return out, ms
+
+
+def variance_time_stats(plain, other, n_boot=500, seed=0):
+    """Gradient variance x time of two samplers over the same views.
+    plain / other: lists (one per view) of (samples [K, N], time_ms). The
+    variance is the per-entry sample variance across seeds summed over entries
+    and views; the time the mean over views of each view's time. Returns the
+    gain (plain / other) with a bootstrap 95% interval (seeds resampled with
+    replacement per view and sampler, times held fixed), and a per-entry Welch
+    test of equal means (fraction of (view, entry) pairs beyond 4 standard
+    errors)."""
+    def var_sum(G, idx=None):
+        X = G if idx is None else G[idx]
+        return float(X.var(0, unbiased=True).sum())
+
+    vp = sum(var_sum(G) for G, _ in plain)
+    vo = sum(var_sum(G) for G, _ in other)
+    tp = sum(t for _, t in plain) / len(plain)
+    to = sum(t for _, t in other) / len(other)
+    gain = (vp * tp) / (vo * to) if vo * to > 0 else float("nan")
+    gen = torch.Generator(device=plain[0][0].device).manual_seed(seed)
+    boots = []
+    for _ in range(n_boot):
+        bp = bo = 0.0
+        for (G, _), (H, _) in zip(plain, other):
+            K, L = G.shape[0], H.shape[0]
+            bp += var_sum(G, torch.randint(0, K, (K,), device=G.device, generator=gen))
+            bo += var_sum(H, torch.randint(0, L, (L,), device=H.device, generator=gen))
+        boots.append((bp * tp) / (bo * to) if bo > 0 else float("nan"))
+    boots = sorted(boots)
+    lo, hi = boots[int(0.025 * n_boot)], boots[int(0.975 * n_boot) - 1]
+    beyond = total = 0
+    for (G, _), (H, _) in zip(plain, other):
+        se = torch.sqrt(G.var(0) / G.shape[0] + H.var(0) / H.shape[0])
+        ok = se > 0
+        z = (G.mean(0) - H.mean(0)).abs()[ok] / se[ok]
+        beyond += int((z > 4).sum())
+        total += int(ok.sum())
+    return {"var_plain": vp, "var_other": vo, "ms_plain": tp, "ms_other": to, "gain": gain,
+            "gain_ci95": [lo, hi], "welch_beyond_4se": beyond, "welch_entries": total}
+
+
 def seconds() -> float:
     torch.cuda.synchronize()
     return time.perf_counter()
+
+
+def propose_ms(scene: api.Scene, prop: "EdgeProposal", cam, reps=5) -> float:
+    """Median time of one proposal (edge features, network, softmax) in ms."""
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        prop.propose(scene, cam)
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[len(ts) // 2]
+
+
+def evaluate_protocol(scene: api.Scene, prop: "EdgeProposal", views, depth, seeds, mix=0.8, d_image=1.0,
+                      n_boot=500) -> dict:
+    """The learned mixture against the plain sampler on held-out views: per
+    term (primary edges, secondary edges, whole gradient) the variance x time
+    gain with a bootstrap 95% interval and a Welch test of equal means. The
+    learned sampler's time includes its proposal (features, network,
+    softmax); times are medians over seeds."""
+    out = {}
+    qs = [prop.propose(scene, cam) for cam, _ in views]
+    pms = [propose_ms(scene, prop, cam) for cam, _ in views]
+    for name, terms, mterms in (("primary", 2, 2), ("secondary", 4, 4), ("total", 0, 6)):
+        plain, learned = [], []
+        for i, (cam, spp) in enumerate(views):
+            G, ta = gradient_samples(scene, cam, spp, depth, [s + 10007 * i for s in seeds], terms=terms,
+                                     d_image=d_image)
+            H, tb = gradient_samples(scene, cam, spp, depth, [s + 10007 * i + 5003 for s in seeds], edge_pdf=qs[i],
+                                     mix=mix, mix_terms=mterms, terms=terms, d_image=d_image)
+            plain.append((G, sorted(ta)[len(ta) // 2]))
+            learned.append((H, sorted(tb)[len(tb) // 2] + pms[i]))
+        out[name] = variance_time_stats(plain, learned, n_boot=n_boot)
+    out["propose_ms"] = sum(pms) / len(pms)
+    return out
 
 
 def evaluate(scene: api.Scene, prop: EdgeProposal, views, depth, seeds, mix=0.8, d_image=1.0) -> dict:

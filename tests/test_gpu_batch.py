@@ -149,3 +149,50 @@ def test_batched_inverse_rendering_recovers_perturbed_vertices():
     assert e1 < 0.6 * e0
     B.close()
     S.close()
+
+
+def test_refit_that_folds_coplanar_faces_rebuilds_the_hierarchy():
+    """Lowering one corner of the ground quad folds its two coplanar faces
+    (their shared diagonal was no discontinuity) into a crease. The refit must
+    flag the batch, the check must rebuild the hierarchies, and the batch's
+    gradient must then equal that of a batch built from scratch on a scene
+    with the moved vertices. A refit that moves only soup triangles (whose
+    edges are all boundary edges) flags nothing."""
+    import copy
+
+    from paper_1904_12228_amd import api, batch
+    cfg = sg.soup(seed=3, n_tris=40, width=64, height=64, spp=4)
+    views = _views(cfg)
+    S = api.Scene(cfg.scene)
+    B = batch.Batch(S, views, 1, seed=7)
+
+    def grads(Bx):
+        for i, (cam, spp) in enumerate(views):
+            x0, y0, x1, y1 = cam.win()
+            Bx.d_images[i].copy_(torch.as_tensor(np.random.default_rng(i).normal(size=(y1 - y0, x1 - x0)) + 0.5))
+        dv = torch.empty((S.num_vertices, 3), dtype=torch.float32, device="cuda")
+        Bx.forward()
+        Bx.backward(dv)
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in Bx.images], dv.cpu().numpy()
+
+    v = S.vertices.clone()
+    v[:3 * 40] += 0.01                       # soup triangles only
+    batch.scene_refit(S, v.contiguous())
+    B.refit()
+    assert not B.check_hierarchy()
+    v[3 * 40 + 1, 1] -= 0.3                  # a ground corner off the diagonal down: the diagonal becomes a crease
+    batch.scene_refit(S, v.contiguous())
+    B.refit()
+    assert B.check_hierarchy()
+    assert not B.check_hierarchy()           # flag cleared by the rebuild
+    imgs, dv = grads(B)
+    moved = copy.deepcopy(cfg.scene)
+    moved.vertices = v.cpu().numpy().astype(np.float32)
+    S2 = api.Scene(moved)
+    B2 = batch.Batch(S2, views, 1, seed=7)
+    imgs2, dv2 = grads(B2)
+    for i in range(len(views)):
+        _close(f"image {i}", imgs[i], imgs2[i], rel=1e-5, floor=1e-7)
+    _close("d_vertices", dv, dv2)
+    B.close(); B2.close(); S.close(); S2.close()

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0):
+def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0, edge_t=0):
     from paper_1904_12228_amd import api
     x0, y0, x1, y1 = cam.win()
     rng = np.random.default_rng(dimg_seed)
@@ -27,15 +27,17 @@ def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0):
         kw = dict(interior=bool(terms & 1), primary=bool(terms & 2), secondary=bool(terms & 4))
     if aov:
         kw["aov"] = aov
+    if edge_t:
+        kw["edge_t"] = edge_t
     print(f"case: V={scene.num_vertices} T={scene.num_triangles} win={cam.win()} spp={spp} depth={depth} seed={seed}"
-          f" aov={aov}", flush=True)
+          f" aov={aov} edge_t={edge_t}", flush=True)
     orc = oracle_reference(scene, cam, spp, depth, seed, dimg, threads=threads, **kw)
     assert orc["stats"][4] == 0, "camera-level near tie in edge classification"
     mask = torch.as_tensor(orc["mask"], device="cuda")
     S = api.Scene(scene)
     img = S.render(cam, spp, depth, seed, unit_mask=mask, aov=aov)
     dv, da, dc = S.render_backward(cam, spp, depth, torch.as_tensor(dimg, dtype=torch.float32, device="cuda"),
-                                   seed=seed, terms=terms, unit_mask=mask, aov=aov)
+                                   seed=seed, terms=terms, unit_mask=mask, aov=aov, edge_t=edge_t)
     torch.cuda.synchronize()
     assert not S.device_error()
     res = dict(img=img.cpu().numpy(), dv=dv.cpu().numpy(), da=da.cpu().numpy(), dc=dc.cpu().numpy())
@@ -43,10 +45,12 @@ def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0):
     flagged = int(orc["stats"][1])
     M = (x1 - x0) * (y1 - y0) * spp
     assert flagged <= 0.05 * M, f"too many near-tie units: {flagged}/{M}"
-    compare("image", res["img"], orc["image"])
-    compare("d_vertices", res["dv"], orc["d_vertices"], orc["mass_vertices"])
-    compare("d_albedo", res["da"], orc["d_albedo"], orc["mass_albedo"])
-    compare("d_camera", res["dc"], orc["d_camera"], orc["mass_camera"])
+    case = (f"T={scene.num_triangles} win={cam.win()} spp={spp} depth={depth} terms={terms or 7} edge_t={edge_t}"
+            f" flagged={flagged}/{M}")
+    compare("image", res["img"], orc["image"], case=case)
+    compare("d_vertices", res["dv"], orc["d_vertices"], orc["mass_vertices"], case=case)
+    compare("d_albedo", res["da"], orc["d_albedo"], orc["mass_albedo"], case=case)
+    compare("d_camera", res["dc"], orc["d_camera"], orc["mass_camera"], case=case)
     return res, orc
 
 
@@ -90,3 +94,23 @@ def test_config3_scene_window(win):
     cfg = sg.config3()
     cam = cfg.camera.with_window(*win)
     _run(cfg.scene, cam, 2, 3, 0)
+
+
+@pytest.mark.parametrize("terms", [4, 7])
+def test_cosine_edge_points_soup(terms):
+    """Secondary edge points drawn by the clamped cosine (edge_t = 1)."""
+    cfg = sg.soup(seed=3, n_tris=40, width=96, height=80, spp=2)
+    cam = cfg.camera.with_window(20, 15, 67, 52)
+    _run(cfg.scene, cam, 2, 1, 5, terms=terms, edge_t=1)
+
+
+def test_cosine_edge_points_sphere_box_depth3():
+    cfg = sg.sphere_box(seed=1, level=3, width=64, height=64, spp=2, max_depth=3)
+    cam = cfg.camera.with_window(6, 10, 49, 41)
+    _run(cfg.scene, cam, 2, 3, 2, edge_t=1)
+
+
+def test_cosine_edge_points_config3_window():
+    cfg = sg.config3()
+    cam = cfg.camera.with_window(300, 200, 331, 225)
+    _run(cfg.scene, cam, 2, 3, 0, edge_t=1)
