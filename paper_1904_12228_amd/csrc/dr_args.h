@@ -44,8 +44,9 @@ struct SideQuery {
     float p[3], wp[3], wm[3];    // shading point, directions just off the edge on both sides
     uint32_t sid;                // pixel-sample id (Philox counter word)
     int edge;
-    float pdf;
+    float pdf;                   // probability of the edge
     int k;                       // path vertex (0 = first hit)
+    float te, pdf_t;             // edge parameter of the point and its density
 };
 
 struct SplitArgs {

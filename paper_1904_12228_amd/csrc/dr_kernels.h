@@ -941,7 +941,11 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     v3 pa = ld3(s.P, e.x), pb = ld3(s.P, e.y);
                     // the point on the edge: uniform in t, or by the clamped cosine
                     float te = b0.y, pdf_t = 1.0f;
-                    if (a.edge_t == 1) {
+                    if (PH == 2) {
+                        // the sampling pass's point (no transcendentals here)
+                        te = sp.q[qi].te;
+                        pdf_t = sp.q[qi].pdf_t;
+                    } else if (a.edge_t == 1) {
                         float Tc;
                         if (!cosine_edge_t(p, n, pa, pb, b0.y, te, Tc)) break;
                         pdf_t = cosine_edge_pdf(p, n, pa, pb, te, Tc);
@@ -977,6 +981,8 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                         Q.edge = ei;
                         Q.pdf = pdf;
                         Q.k = kk;
+                        Q.te = te;
+                        Q.pdf_t = pdf_t;
                         sp.q[slot] = Q;
                         sp.qidx[(size_t)kk * a.M + m] = slot;
                         break;
@@ -1142,6 +1148,124 @@ __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArg
     __shared__ int stk[STK * BS];
     MixArgs mx{};
     backward_body<MAXD, STK, false, false, 1>(s, k, a, tv, nullptr, nullptr, nullptr, nullptr, mx, blockIdx.x * BS, stk, sp);
+}
+
+// Split backward, pass 1, one lane per (path vertex, unit) when every vertex
+// the pass needs is checkpointed (kernel depth <= 3): items are vertex-major
+// (item = kk * M + m), so a unit's edge-tree descents, each a chain of
+// dependent node fetches, run in parallel lanes instead of one after another.
+// Each lane rebuilds its unit's path up to its vertex with the adjoint pass's
+// arithmetic (same operations in the same order) and appends its side-path
+// query to segment kk of the queue.
+template <int STK>
+__global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
+                                                     int nvert) {
+    __shared__ int stk[STK * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    NoWork wk;
+    long item = (long)blockIdx.x * BS + lane;
+    int kk = (int)(item / a.M);
+    int m = (int)(item - (long)kk * a.M);
+    bool in = kk < nvert;
+    if (in) sp.qidx[(size_t)kk * a.M + m] = -1;
+    bool push = false;
+    SideQuery Q;
+    if (in && (!a.mask || a.mask[m]) && a.depth >= kk + 1 && a.ck_tri[m] >= 0 && tv.valid &&
+        (a.terms & DR_TERM_SECONDARY)) {
+        int pix, px, py;
+        uint32_t sid;
+        unit_pixel(k, a, m, pix, px, py, sid);
+        Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
+        float4 j = rc.block(0);
+        float sx = px + j.x, sy = py + j.y;
+        float ndx = 2.0f * sx / k.W - 1.0f, ndy = 1.0f - 2.0f * sy / k.H;
+        v3 d = k.f + k.r * (ndx * k.asp * k.th) + k.u * (ndy * k.th);
+        // the path up to vertex kk, as the adjoint pass rebuilds it
+        int t = a.ck_tri[m];
+        v3 x = {a.ck_x[3 * (size_t)m], a.ck_x[3 * (size_t)m + 1], a.ck_x[3 * (size_t)m + 2]};
+        v3 n = {0, 0, 0};
+        bool alive = false;
+        for (int jj = 0; jj <= kk; ++jj) {
+            TriGeom g = tri_geom(s, t);
+            float sgn = dot(d, cross(g.e1, g.e2)) < 0.0f ? 1.0f : -1.0f;
+            n = shading_normal(s, t, g, x) * sgn;
+            if (s.alb[t] == 0.0f) break;
+            if (jj == kk) {
+                alive = true;
+                break;
+            }
+            float4 ub = rc.block(2 * jj + 2);
+            v3 w = cosine_dir(n, ub.x, ub.y);
+            if (dot(n, w) <= 0.0f) break;
+            int t2 = a.ck_tri[(size_t)(jj + 1) * a.M + m];
+            if (t2 < 0) break;
+            const float* cx = a.ck_x + 3 * ((size_t)(jj + 1) * a.M + m);
+            v3 x2 = {cx[0], cx[1], cx[2]};
+            if (s.alb[t2] == 0.0f) break;
+            d = w;
+            t = t2;
+            x = x2;
+        }
+        if (alive) {
+            Rng rk{sid, a.view, kTagSedge + (uint32_t)(kk + 1), a.k0, a.k1};
+            float4 b0 = rk.block(0);
+            v3 p = x;
+            float pdf;
+            TreeCtx q = tree_ctx(&s, p, n, tv.cam, t, kHorizon * s.diag, kInsidePad * s.diag);
+            int ei = tree_sample(tv, q, rk, b0.x, pdf, wk, m == a.debug_unit);
+            do {
+                if (ei < 0) break;
+                int4 e = s.edges[ei];
+                if (e.z == t || e.w == t) break;
+                if (s.ekind[ei] == 2 && !silhouette_from(s, e, p)) break;
+                v3 pa = ld3(s.P, e.x), pb = ld3(s.P, e.y);
+                float te = b0.y, pdf_t = 1.0f;
+                if (a.edge_t == 1) {
+                    float Tc;
+                    if (!cosine_edge_t(p, n, pa, pb, b0.y, te, Tc)) break;
+                    pdf_t = cosine_edge_pdf(p, n, pa, pb, te, Tc);
+                    if (!(pdf_t > 0.0f)) break;
+                }
+                v3 w = pa + (pb - pa) * te - p;
+                if (dot(n, w) <= kHorizon * s.diag) break;
+                v3 c = cross(pa - p, pb - p);
+                float cn = len(c);
+                if (cn == 0.0f) break;
+                v3 nh = c * (1.0f / cn);
+                v3 wh = w * (1.0f / len(w));
+                v3 wp = nrm(wh + nh * kEps3), wm = nrm(wh - nh * kEps3);
+                Q.p[0] = p.x; Q.p[1] = p.y; Q.p[2] = p.z;
+                Q.wp[0] = wp.x; Q.wp[1] = wp.y; Q.wp[2] = wp.z;
+                Q.wm[0] = wm.x; Q.wm[1] = wm.y; Q.wm[2] = wm.z;
+                Q.sid = sid;
+                Q.edge = ei;
+                Q.pdf = pdf;
+                Q.k = kk;
+                Q.te = te;
+                Q.pdf_t = pdf_t;
+                push = true;
+            } while (false);
+        }
+    }
+    // append to the queue segment of each lane's vertex: one atomic per
+    // (wave, vertex); a wave spans more than one vertex only at segment ends
+    unsigned long long left = __ballot(push);
+    while (left) {
+        int leader = __ffsll(left) - 1;
+        int kl = __shfl(kk, leader, BS);
+        bool mine = push && kk == kl;
+        unsigned long long bal = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&sp.count[kl], __popcll(bal));
+        base = __shfl(base, leader, BS);
+        if (mine) {
+            int slot = kl * a.M + base + __popcll(bal & ((1ull << lane) - 1ull));
+            sp.q[slot] = Q;
+            sp.qidx[(size_t)kk * a.M + m] = slot;
+        }
+        left &= ~bal;
+    }
 }
 
 // Split backward, pass 2: both one-sided radiances of every queued query, one
