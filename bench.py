@@ -192,13 +192,17 @@ def gbuffer_leg(S, cam, spp, d_image, reps=3):
             **res}
 
 
+# Adam learning rate by step for the inverse-rendering leg (piecewise constant)
+INVERSE_SCHEDULE = [(0, 1e-3), (100, 5e-4), (150, 2.5e-4)]
+
+
 def inverse_leg(steps=200):
     """Batched inverse rendering on the 1,000-triangle scene: 32 seeded views
     (128^2 to 512^2, 8 to 64 spp, depth 1) in one batch, target images of the
-    true scene, the soup's vertices perturbed by N(0, 0.02^2) per coordinate,
-    then `steps` Adam steps, each refit -> render -> loss gradient -> backward
-    -> Adam captured once as a HIP graph and replayed; launch shape from the
-    autotuner."""
+    true scene at 256 spp, the soup's vertices perturbed by N(0, 0.02^2) per
+    coordinate, then `steps` Adam steps (learning rate INVERSE_SCHEDULE), each
+    render -> loss gradient -> backward -> Adam -> refit captured as a HIP
+    graph and replayed; launch shape from the autotuner."""
     import torch
 
     from paper_1904_12228_amd import api, batch, scenegen
@@ -212,7 +216,7 @@ def inverse_leg(steps=200):
         d.fill_(1.0)
     tune = batch.autotune(B, reps=1, use_cache=False)
     true_v = S.vertices.clone()
-    T = batch.Batch(S, views, 1, seed=999)
+    T = batch.Batch(S, [(c, 256) for c, _ in views], 1, seed=999)
     T.set_launch(*B.launch)
     T.forward()
     targets = [t.clone() for t in T.images]
@@ -231,9 +235,9 @@ def inverse_leg(steps=200):
     thr = 1e-2 * float(n_infl[soup].max())
     mask = (soup & (n_infl > thr)).float()
     v0 = (true_v + 0.02 * torch.randn(true_v.shape, device="cuda", generator=g) * mask[:, None]).contiguous()
-    inv = batch.InverseRendering(B, v0, targets, mask, lr=2e-3)
+    inv = batch.InverseRendering(B, v0, targets, mask, schedule=INVERSE_SCHEDULE)
     err = lambda: float(((inv.v - true_v) ** 2 * mask[:, None]).sum().sqrt())
-    e0 = err()
+    curve = {0: err()}
     t0 = time.perf_counter()
     inv.step()
     loss0 = inv.loss()
@@ -241,14 +245,16 @@ def inverse_leg(steps=200):
     eager_ms = (time.perf_counter() - t0) * 1e3
     inv.capture()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(steps - 2):
+    graph_ms = 0.0
+    for i in range(inv.steps_done, steps):
+        t1 = time.perf_counter()
         inv.step()
-        if i % 50 == 49:
-            torch.cuda.synchronize()
-            print(f"inverse rendering: step {i + 3}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - t1) * 1e3 / (steps - 2)
+        torch.cuda.synchronize()
+        graph_ms += (time.perf_counter() - t1) * 1e3
+        if inv.steps_done in (50, 100, 150, 200):
+            curve[inv.steps_done] = err()
+            print(f"inverse rendering: step {inv.steps_done}", file=sys.stderr, flush=True)
+    graph_ms /= max(steps - 2, 1)
     e1 = err()
     loss = inv.loss()
     B.close()
@@ -257,7 +263,9 @@ def inverse_leg(steps=200):
                         "Adam on the observed soup vertices from a N(0, 0.02^2) perturbation",
             "observed_vertices": int(mask.sum()), "samples_per_step": B.samples, "steps": steps, "ms_per_step_graph": graph_ms,
             "ms_per_step_eager_first": eager_ms, "samples_per_s": B.samples / (graph_ms * 1e-3),
-            "autotune": tune, "vertex_error": [e0, e1], "image_loss": [loss0, loss]}
+            "autotune": tune, "lr_schedule": INVERSE_SCHEDULE, "vertex_error": [curve[0], e1],
+            "vertex_error_by_step": curve, "error_ratio": e1 / curve[0], "hierarchy_rebuilds": inv.rebuilds,
+            "image_loss": [loss0, loss]}
 
 
 def main():

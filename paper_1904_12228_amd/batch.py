@@ -151,7 +151,7 @@ class InverseRendering:
     changed discontinuity class, rebuilds the hierarchies (and captures the
     graph again) before the next step renders."""
 
-    def __init__(self, batch: Batch, vertices0: torch.Tensor, targets, mask: torch.Tensor, lr=2e-3):
+    def __init__(self, batch: Batch, vertices0: torch.Tensor, targets, mask: torch.Tensor, lr=2e-3, schedule=None):
         dev = batch.scene.device
         self.b = batch
         self.v = vertices0.detach().clone().contiguous()
@@ -161,7 +161,11 @@ class InverseRendering:
         self.m = torch.zeros_like(self.v)
         self.s = torch.zeros_like(self.v)
         self.step_count = torch.zeros(1, dtype=torch.int64, device=dev)
-        self.lr = float(lr)
+        # learning-rate schedule: [(first step, lr), ...], piecewise constant;
+        # a change re-captures the graph (its Adam launch carries the rate)
+        self.schedule = sorted((int(k), float(v)) for k, v in (schedule or [(0, lr)]))
+        self.lr = self.schedule[0][1]
+        self.steps_done = 0
         self.scale = [2.0 / t.numel() for t in self.targets]
         self.graph = None
         self.rebuilds = 0
@@ -191,11 +195,24 @@ class InverseRendering:
         scene_refit(b.scene, self.v)
         b.refit()
 
+    def _lr_at(self, k):
+        lr = self.schedule[0][1]
+        for first, v in self.schedule:
+            if k >= first:
+                lr = v
+        return lr
+
     def step(self):
+        lr = self._lr_at(self.steps_done)
+        if lr != self.lr:
+            self.lr = lr
+            if self.graph is not None:
+                self._capture_only()
         if self.graph is not None:
             self.graph.replay()
         else:
             self._step()
+        self.steps_done += 1
         self._check()
 
     def _capture_only(self):
@@ -209,10 +226,13 @@ class InverseRendering:
         capture stream, which also advances the optimisation by one step)."""
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
+        self.lr = self._lr_at(self.steps_done)
         with torch.cuda.stream(side):
             self._step()
         torch.cuda.current_stream().wait_stream(side)
+        self.steps_done += 1
         self._check()
+        self.lr = self._lr_at(self.steps_done)
         self._capture_only()
         return self.graph
 

@@ -660,7 +660,7 @@ __global__ void k_etree_links(const int2* __restrict__ child, int n, int base, i
     nd->child[0] = c.x < 0 ? ~list_s[~c.x] : base + c.x;
     nd->child[1] = c.y < 0 ? ~list_s[~c.y] : base + c.y;
     nd->h2 = is_h2;
-    nd->pad = 0;
+    nd->pad[0] = nd->pad[1] = nd->pad[2] = 0;
     counter[i] = 0;
 }
 

@@ -139,12 +139,13 @@ struct ETChild {
     float lo[3], hi[3], len;
     float hlo0[3], hhi0[3], hlo1[3], hhi1[3];
 };
-struct ETNode {
+struct alignas(16) ETNode {
     ETChild ch[2];
     int child[2];            // >= 0: internal node index; < 0: ~edge id (leaf)
     int h2;                  // 1 if this node belongs to the Hough-space hierarchy
-    int pad;
+    int pad[3];              // 176 bytes: eleven 16-byte loads fetch a node
 };
+static_assert(sizeof(ETNode) == 176, "edge hierarchy node layout");
 
 struct TreeView {
     const ETNode* nodes;     // [0] = virtual root whose children are the H1 and H2 roots

@@ -22,6 +22,9 @@
 #include "dr_path.h"
 
 #pragma clang diagnostic ignored "-Wunused-function"
+// Per-sample device printf of the unit RenderArgs::debug_unit names (primary
+// edge sample, edge-tree levels, secondary samples) is compiled only with
+// -DDIFFRT_DEVICE_PRINTF: the printf machinery costs the kernels registers.
 
 namespace dr {
 
@@ -458,9 +461,11 @@ __device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, c
                 jumps = fu != fl;
                 if (jumps) jump = dI[0] * (fu - fl);
             }
+#ifdef DIFFRT_DEVICE_PRINTF
             if (m == a.debug_unit)
                 printf("punit %d edge %d x %.9g y %.9g A %.9g %.9g B %.9g %.9g jump %.9g total %.9g\n", m, G.ei, G.x,
                        G.y, G.Ax, G.Ay, G.Bx, G.By, jump, total);
+#endif
             if (jumps) {
                 prim_contrib(k, a, G, jump, gv, ca);
                 have = true;
@@ -656,6 +661,18 @@ __device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, 
     return c.len * b / len(ctr - q.p);
 }
 
+// A whole node in registers: its eleven 16-byte words are loaded together,
+// so a level waits for memory once instead of once per field it reads.
+__device__ inline ETNode load_node(const ETNode* __restrict__ nodes, int i) {
+    const float4* p = reinterpret_cast<const float4*>(nodes + i);
+    float4 w[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) w[k] = p[k];
+    ETNode n;
+    __builtin_memcpy(&n, w, sizeof(ETNode));
+    return n;
+}
+
 template <class W>
 __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rng& rk, float u_root, float& pdf, W& wk,
                                   bool dbg = false) {
@@ -673,7 +690,7 @@ __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rn
     int level = -1;
     float4 ub = make_float4(0, 0, 0, 0);
     while (true) {
-        const ETNode& N = nodes[node];
+        const ETNode N = load_node(nodes, node);
         wk.tree();
         int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
         float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
@@ -691,7 +708,9 @@ __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rn
         float p0 = w0 / tot;
         int side = u < p0 ? 0 : 1;
         pdf *= side == 0 ? p0 : w1 / tot;
+#ifdef DIFFRT_DEVICE_PRINTF
         if (dbg) printf("  level %d node %d w0 %.9g w1 %.9g u %.9g side %d\n", level, node, w0, w1, u, side);
+#endif
         int ref = N.child[side];
         if (ref < 0) return ~ref;
         for (int k = 0; k < 3; ++k) { plo[k] = N.ch[side].lo[k]; phi[k] = N.ch[side].hi[k]; }
@@ -710,7 +729,7 @@ __device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int 
     int node = code >> 1, side = code & 1;
     float pdf = 1.0f;
     for (int guard = 0; guard <= kMaxLevels + 1; ++guard) {
-        const ETNode& N = nodes[node];
+        const ETNode N = load_node(nodes, node);
         wk.tree();
         int pcode = node == 0 ? -1 : tv.enpar[node];
         float plo[3], phi[3];
@@ -1000,10 +1019,12 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     if (Fp == Fm) break;
                     float Wk = d_image[pix] * beta[kk] / (float)a.spp;
                     float wgt = Wk * (Fp - Fm) * len(cross(pb - pa, wh)) / (cn * wl * pdf * pdf_t);
+#ifdef DIFFRT_DEVICE_PRINTF
                     if (dbg)
                         printf("unit %d vertex %d tri %d p=(%.9g %.9g %.9g) n=(%.9g %.9g %.9g) edge %d pdf %.9g t %.9g Lp %.9g "
                                "Lm %.9g cos %.9g W %.9g wgt %.9g\n",
                                m, kk + 1, tri[kk], p.x, p.y, p.z, n.x, n.y, n.z, ei, pdf, te, Lp, Lm, cosw, Wk, wgt);
+#endif
                     if (PH == 2) {
                         v3 c0 = cross(v1p, wh) * wgt, c1 = cross(wh, v0p) * wgt;
                         bedge = ei;
@@ -1160,9 +1181,8 @@ __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArg
 template <int STK>
 __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
                                                      int nvert) {
-    __shared__ int stk[STK * BS];
+    // no rays are traced here: no traversal stack (STK only names the variant)
     int lane = threadIdx.x;
-    int* my = stk + lane;
     NoWork wk;
     long item = (long)blockIdx.x * BS + lane;
     int kk = (int)(item / a.M);
