@@ -55,7 +55,7 @@ typedef struct drScene_t* drScene;
  * drSceneCreate only (the library copies what it needs). */
 typedef struct {
     int32_t num_vertices;        /* V >= 3 */
-    int32_t num_triangles;       /* T >= 1 */
+    int32_t num_triangles;       /* 1 <= T <= 2^26 (larger: DR_ERROR_INVALID_VALUE) */
     const float*   vertices;     /* [V][3] world-space positions */
     const int32_t* indices;      /* [T][3] vertex indices, 0 <= i < V */
     const float*   normals;      /* [V][3] shading normals, or NULL for flat shading */

@@ -116,6 +116,8 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     *out = nullptr;
     if (d->num_vertices < 3 || d->num_triangles < 1 || !d->vertices || !d->indices || !d->albedo || !d->emission)
         return DR_ERROR_INVALID_VALUE;
+    // traversal addresses triangle records and tree nodes by 32-bit byte offsets
+    if (d->num_triangles > kMaxTriangles) return DR_ERROR_INVALID_VALUE;
     int V = d->num_vertices, T = d->num_triangles;
     std::vector<int> I(3 * (size_t)T);
     std::vector<float> emi(T);
@@ -164,9 +166,18 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     // triangle BVH topology: binned SAH on the host (default) or Morton-code LBVH on the device
     if (const char* e = std::getenv("DIFFRT_BVH")) s->sah_bvh = std::strcmp(e, "lbvh") != 0;
     s->hI = I;
+    // gradient copies: FP32 atomics are performed beyond the L2, where updates
+    // of one address serialise; 256 copies spread the hot entries (large
+    // triangles hit by many paths), halved while all copies exceed 256 MiB
+    {
+        long copy_bytes = 4L * (3L * V + T);
+        int k = 256;
+        while (k > 1 && (long)k * copy_bytes > (256L << 20)) k >>= 1;
+        s->grad_shards = k;
+    }
     if (const char* e = std::getenv("DIFFRT_GRAD_SHARDS")) {
         int k = std::atoi(e);
-        if (k >= 1 && k <= 64 && (k & (k - 1)) == 0) s->grad_shards = k;
+        if (k >= 1 && k <= 1024 && (k & (k - 1)) == 0) s->grad_shards = k;
     }
     API_CHECK(hipGetDevice(&s->device));
     auto fail = [&](drStatus e) {

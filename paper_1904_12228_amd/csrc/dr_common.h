@@ -20,6 +20,8 @@ constexpr float kHorizon = 1e-5f;     // edge points this * diagonal below/at th
 constexpr float kVsphereMargin = 1e-5f;  // v-sphere pruning only beyond this relative margin
 constexpr float kPi = 3.14159265358979323846f;
 constexpr int kMaxDepth = 6;
+constexpr int kMaxTriangles = 1 << 26;  // 64 B tree nodes and 48 B triangle records stay below 4 GiB
+constexpr int kQueueBlocks = 8192;      // persistent grid of the kernels that drain a work queue
 constexpr int kStackDepth = 64;       // largest BVH traversal stack (entries per lane)
 constexpr int kMaxLevels = 64;        // edge-tree descent levels (16 Philox blocks x 4)
 constexpr int kSideBlockBase = 32;    // Philox block base of secondary side paths

@@ -55,7 +55,7 @@ struct drScene_t {
     float background = 0.0f;
     float diag = 0.0f, tmin = 0.0f, atot = 0.0f;
     int bvh_depth = 0;               // internal nodes on the longest root-to-leaf path
-    int grad_shards = 16;            // copies of the gradient arrays (power of two; see launch_backward)
+    int grad_shards = 256;           // copies of the gradient arrays (power of two; set by drSceneCreate)
     uint64_t version = 0;            // bumps on every vertex update
     // scene data
     dr::Buf P, I, N, alb, emi, tri, bvh, edges, ekind, lights, lcdf, scal, err;

@@ -492,24 +492,25 @@ __device__ __forceinline__ void primary_body(const SceneView& s, const Cam& k, c
 // and the first hits of its two side rays (one traversal for both); samples
 // whose sides hit the same triangle contribute nothing and stop here, the
 // others are appended to a compact queue (one atomic per wave).
-template <int STK>
+template <int STK, bool MIX>
 __global__ __launch_bounds__(BS) void k_prim_sample(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
                                                     const double* __restrict__ cdf, int3* __restrict__ q,
-                                                    int* __restrict__ count) {
+                                                    int* __restrict__ count, MixArgs mx) {
     __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
     int m = blockIdx.x * BS + lane;
     NoWork wk;
-    MixArgs mx{};
     bool push = false;
     Hit hu, hl;
     if (m < a.M && (!a.mask || a.mask[m]) && cdf[s.E] > 0.0) {
         Rng rp{(uint32_t)m, a.view, kTagPedge, a.k0, a.k1};
         float4 b0 = rp.block(0);
-        PrimGeom G = prim_geom<false>(s, k, a, pe, cdf, mx, m, b0);
-        trace_closest2(s, k.c, G.du, G.dl, k.nearc, 3.0e38f, my, BS, wk, hu, hl);
-        push = hu.tri != hl.tri;
+        PrimGeom G = prim_geom<MIX>(s, k, a, pe, cdf, mx, m, b0);
+        if (G.live) {
+            trace_closest2(s, k.c, G.du, G.dl, k.nearc, 3.0e38f, my, BS, wk, hu, hl);
+            push = hu.tri != hl.tri;
+        }
     }
     unsigned long long bal = __ballot(push);
     if (bal == 0ull) return;
@@ -523,17 +524,17 @@ __global__ __launch_bounds__(BS) void k_prim_sample(SceneView s, Cam k, RenderAr
 // Split primary pass, 2 of 2: the queued samples, densely: both sides'
 // camera paths from their first hits (same random numbers), the jump, and
 // the endpoint and camera gradients (lanes drawing the same edge summed in
-// the wave before the atomics).
-template <int STK>
+// the wave before the atomics). MIX: the learned-proposal mixture's edge
+// choice and, when asked, the per-edge harvest statistic.
+template <int STK, bool MIX>
 __global__ __launch_bounds__(BS, 4) void k_prim_paths(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
                                                    const double* __restrict__ cdf, const int3* __restrict__ q,
                                                    const int* __restrict__ count, const float* __restrict__ d_image,
-                                                   float* __restrict__ dV, float* __restrict__ camacc) {
+                                                   float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {
     __shared__ int stk[STK * BS];
     int lane = threadIdx.x;
     int* my = stk + lane;
     NoWork wk;
-    MixArgs mx{};
     CamAcc ca = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     int sh = blockIdx.x & (a.gshards - 1);
     dV += sh * a.gstride;
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(BS, 4) void k_prim_paths(SceneView s, Cam k, Render
             {
                 // only the two ray directions stay live across the paths; the
                 // rest of the sample's geometry is recomputed afterwards
-                PrimGeom G = prim_geom<false>(s, k, a, pe, cdf, mx, m, b0);
+                PrimGeom G = prim_geom<MIX>(s, k, a, pe, cdf, mx, m, b0);
                 du = G.du;
                 dl = G.dl;
             }
@@ -560,11 +561,17 @@ __global__ __launch_bounds__(BS, 4) void k_prim_paths(SceneView s, Cam k, Render
             float fu = radiance_hit(s, rp, 0, k.c, du, hu, true, a.depth, my, BS, wk);
             float fl = radiance_hit(s, rp, 0, k.c, dl, hl, true, a.depth, my, BS, wk);
             if (fu != fl) {
-                PrimGeom G = prim_geom<false>(s, k, a, pe, cdf, mx, m, b0);
+                PrimGeom G = prim_geom<MIX>(s, k, a, pe, cdf, mx, m, b0);
                 float jump = d_image[G.pix] * (fu - fl);
                 prim_contrib(k, a, G, jump, gv, ca);
                 have = true;
                 key = G.ei;
+                if (MIX && mx.estats) {
+                    float c2 = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) c2 += gv[i] * gv[i];
+                    atomicAdd(&mx.estats[G.ei], (float)G.p_edge * c2);
+                }
             }
         }
         scatter_grouped(have, key, gv, 4, [&](int ek, int i) {
@@ -599,9 +606,11 @@ __device__ inline bool vsphere_prune(const ETChild& c, v3 pc) {
         const float* hi = f == 0 ? c.hhi0 : c.hhi1;
         float d2 = 0.0f, far2 = 0.0f;
         for (int k = 0; k < 3; ++k) {
-            float d = sv[k] < lo[k] ? lo[k] - sv[k] : (sv[k] > hi[k] ? sv[k] - hi[k] : 0.0f);
+            // distance of the centre to the box along k (0 inside) and to its far face
+            float a = lo[k] - sv[k], b = sv[k] - hi[k];
+            float d = fmaxf(fmaxf(a, b), 0.0f);
             d2 += d * d;
-            float fa = fmaxf(fabsf(lo[k] - sv[k]), fabsf(hi[k] - sv[k]));
+            float fa = fmaxf(fabsf(a), fabsf(b));
             far2 += fa * fa;
         }
         out[f] = d2 > r2 * (1.0f + kVsphereMargin);
@@ -621,12 +630,13 @@ __device__ inline float cos_bound(const float lo[3], const float hi[3], v3 p, v3
     float cy = dot(t2, c), ey = fabsf(t2.x) * h.x + fabsf(t2.y) * h.y + fabsf(t2.z) * h.z;
     float zh = dot(n, c) + fabsf(n.x) * h.x + fabsf(n.y) * h.y + fabsf(n.z) * h.z;
     float xl = cx - ex, xh = cx + ex, yl = cy - ey, yh = cy + ey;
-    float dx = (xl <= 0.0f && xh >= 0.0f) ? 0.0f : fminf(fabsf(xl), fabsf(xh));
-    float dy = (yl <= 0.0f && yh >= 0.0f) ? 0.0f : fminf(fabsf(yl), fabsf(yh));
+    // distance of [l, h] from 0: l when above it, -h when below, 0 when it spans 0
+    float dx = fmaxf(fmaxf(xl, -xh), 0.0f);
+    float dy = fmaxf(fmaxf(yl, -yh), 0.0f);
     float dxy2 = dx * dx + dy * dy;
     if (zh <= hz) return 0.0f;
     if (dxy2 == 0.0f) return 1.0f;
-    return zh / sqrtf(dxy2 + zh * zh);
+    return zh * rsqrtf(dxy2 + zh * zh);
 }
 
 struct TreeCtx {
@@ -658,7 +668,8 @@ __device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, 
         if (pv[k] < plo[k] - q.pad || pv[k] > phi[k] + q.pad) in = false;
     if (in) return 1.0f;
     v3 ctr = {(c.lo[0] + c.hi[0]) * 0.5f, (c.lo[1] + c.hi[1]) * 0.5f, (c.lo[2] + c.hi[2]) * 0.5f};
-    return c.len * b / len(ctr - q.p);
+    v3 dc = ctr - q.p;
+    return c.len * b * rsqrtf(dot(dc, dc));
 }
 
 // A whole node in registers: its eleven 16-byte words are loaded together,
@@ -1178,9 +1189,9 @@ __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArg
 // Each lane rebuilds its unit's path up to its vertex with the adjoint pass's
 // arithmetic (same operations in the same order) and appends its side-path
 // query to segment kk of the queue.
-template <int STK>
+template <int STK, bool MIX>
 __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
-                                                     int nvert) {
+                                                     int nvert, MixArgs mx) {
     // no rays are traced here: no traversal stack (STK only names the variant)
     int lane = threadIdx.x;
     NoWork wk;
@@ -1233,8 +1244,24 @@ __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderA
             v3 p = x;
             float pdf;
             TreeCtx q = tree_ctx(&s, p, n, tv.cam, t, kHorizon * s.diag, kInsidePad * s.diag);
-            int ei = tree_sample(tv, q, rk, b0.x, pdf, wk, m == a.debug_unit);
+            int ei;
             do {
+                if (MIX && mx.sec) {
+                    // proposal mixture: component from the third uniform of the
+                    // block, proposal draw from the fourth
+                    float pt;
+                    if (b0.z < mx.mix) {
+                        ei = pick_cdf_d(mx.qcdf, s.E, (double)b0.w);
+                        pt = tree_pdf_edge(tv, q, ei, wk);
+                    } else {
+                        ei = tree_sample(tv, q, rk, b0.x, pt, wk, m == a.debug_unit);
+                        if (ei < 0) break;
+                    }
+                    pdf = mx.mix * mx.q[ei] + (1.0f - mx.mix) * pt;
+                    if (!(pdf > 0.0f) || s.ekind[ei] == 0) break;
+                } else {
+                    ei = tree_sample(tv, q, rk, b0.x, pdf, wk, m == a.debug_unit);
+                }
                 if (ei < 0) break;
                 int4 e = s.edges[ei];
                 if (e.z == t || e.w == t) break;
@@ -1314,15 +1341,15 @@ __global__ __launch_bounds__(BS) void k_side(SceneView s, RenderArgs a, SplitArg
 
 // Split backward, pass 3: boundary contributions from the queued radiances and
 // the adjoint sweep.
-template <int MAXD, int STK>
+template <int MAXD, int STK, bool MIX>
 __global__ __launch_bounds__(BS) void k_bwd_adjoint(SceneView s, Cam k, RenderArgs a, TreeView tv,
                                                     const float* __restrict__ d_image, float* __restrict__ dV,
-                                                    float* __restrict__ dA, float* __restrict__ camacc, SplitArgs sp) {
+                                                    float* __restrict__ dA, float* __restrict__ camacc, SplitArgs sp,
+                                                    MixArgs mx) {
     __shared__ int stk[STK * BS];
     int sh = blockIdx.x & (a.gshards - 1);
-    MixArgs mx{};
-    backward_body<MAXD, STK, false, false, 2>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride,
-                                              camacc + 12 * sh, mx, blockIdx.x * BS, stk, sp);
+    backward_body<MAXD, STK, false, MIX, 2>(s, k, a, tv, d_image, dV + sh * a.gstride, dA + sh * a.gstride,
+                                            camacc + 12 * sh, mx, blockIdx.x * BS, stk, sp);
 }
 
 __device__ inline void cam_finalize(const Cam& k, const float* __restrict__ acc, float* __restrict__ d_camera) {

@@ -2,6 +2,7 @@
 // orchestration in dr_render.hip picks a variant, and the unit that compiles
 // that variant launches it.
 #pragma once
+#include <algorithm>
 #include "dr_args.h"
 #include "dr_host.h"
 
@@ -14,7 +15,7 @@ struct Variant {
 };
 
 // Primary edge samples: one lane per unit (k_primary), or, when `pq` is not
-// null (production variant only), the split pair k_prim_sample (edge sample,
+// null (production and mixture variants), the split pair k_prim_sample (edge sample,
 // first hits, compact queue of the samples whose sides hit different
 // triangles: pq [M], *pcount zeroed first) and k_prim_paths (the queued
 // samples' camera paths and gradients, paths_grid persistent blocks).

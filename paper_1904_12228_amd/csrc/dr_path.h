@@ -13,8 +13,8 @@ namespace dr {
 struct TriGeom { v3 p0, e1, e2; };
 
 __device__ inline TriGeom tri_geom(const SceneView& s, int id) {
-    float4 a = s.tri[3 * id], b = s.tri[3 * id + 1], c = s.tri[3 * id + 2];
-    return {{a.x, a.y, a.z}, {a.w, b.x, b.y}, {b.z, b.w, c.x}};
+    TriRec r = load_tri(s.tri, id);
+    return {{r.a.x, r.a.y, r.a.z}, {r.a.w, r.b.x, r.b.y}, {r.b.z, r.b.w, r.c.x}};
 }
 
 // Point where the ray meets the triangle's plane (moves with the ray and the

@@ -57,13 +57,16 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
         // whose two sides hit different triangles, traced densely
         int3* pq = nullptr;
         int* pcount = nullptr;
-        if (s->split_primary && !v.aov && !v.mix && !v.counters) {
+        if (s->split_primary && !v.aov && !v.counters) {
             if (s->pq.ensure(sizeof(int3) * (size_t)a.M) != hipSuccess || s->pcount.ensure(sizeof(int) * 64) != hipSuccess)
                 return DR_ERROR_OUT_OF_MEMORY;
             pq = s->pq.as<int3>();
             pcount = s->pcount.as<int>();
         }
-        int paths_grid = std::max(1, std::min(nblk((long)a.M, BS), 256 * 16));
+        // persistent grids of the queue kernels: 8,192 blocks (two rounds of
+        // the 4,096 the device holds at once) measured best; 5,120 leaves a
+        // second round a quarter full
+        int paths_grid = std::max(1, std::min(nblk((long)a.M, BS), kQueueBlocks));
         launch_primary_kernel(v, g, sv, cam, a, pe, pc, d_image, dV, camacc, mx, pq, pcount, paths_grid, st);
     }
     if (o.aov) {
@@ -86,7 +89,8 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
         EvScope ev(s, 2, st);
         a.counters = cbase ? cbase + 16 : nullptr;
         dim3 g(nblk(a.M, BS));
-        bool split = !use_mix && !a.counters && s->split_backward;
+        // the split kernels serve the mixture up to kernel depth 3
+        bool split = !a.counters && s->split_backward && (!use_mix || o.max_depth <= 3);
         SplitArgs sp{};
         // queue capacity: MAXD (the kernels' template depth: 1, 3 or 6) slots per unit
         int maxd = o.max_depth <= 1 ? 1 : (o.max_depth <= 3 ? 3 : 6);
@@ -106,7 +110,7 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
             sp.count = s->scount.as<int>();
             k_fill_count<<<1, 64, 0, st>>>(sp.count, maxd);
         }
-        int side_grid = std::max(1, std::min(nblk((long)a.M, BS), 256 * 16));
+        int side_grid = std::max(1, std::min(nblk((long)a.M, BS), kQueueBlocks));
 PathLaunch pl{Variant{false, use_mix, a.counters != nullptr, sm}, split, g, side_grid, o.max_depth, sv, cam, a,
                       tv, sp, d_image, dV, dA, camacc, mx};
         if (o.max_depth <= 1) {

@@ -1,4 +1,5 @@
-// Primary edge samples (k_primary): every variant.
+// Primary edge samples: the split pair (k_prim_sample, k_prim_paths) for the
+// production and mixture variants, k_primary for every variant.
 #include "dr_kernels.h"
 #include "dr_launch.h"
 
@@ -8,15 +9,19 @@ void launch_primary_kernel(const Variant& v, dim3 g, const SceneView& sv, const 
                            const PEdge* pe, const double* pc, const float* d_image, float* dV, float* camacc,
                            const MixArgs& mx, int3* pq, int* pcount, int paths_grid, hipStream_t st) {
     dim3 b(BS);
-    if (pq && !v.aov && !v.mix && !v.counters) {
+    if (pq && !v.aov && !v.counters) {
         k_fill_count<<<1, 64, 0, st>>>(pcount, 1);
-        if (v.small) {
-            k_prim_sample<32><<<g, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount);
-            k_prim_paths<32><<<paths_grid, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, d_image, dV, camacc);
+#define DR_SPLIT(S, X)                                                                                                \
+    k_prim_sample<S, X><<<g, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, mx);                                          \
+    k_prim_paths<S, X><<<paths_grid, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, d_image, dV, camacc, mx)
+        if (v.mix) {
+            if (v.small) { DR_SPLIT(32, true); }
+            else { DR_SPLIT(kStackDepth, true); }
         } else {
-            k_prim_sample<kStackDepth><<<g, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount);
-            k_prim_paths<kStackDepth><<<paths_grid, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, d_image, dV, camacc);
+            if (v.small) { DR_SPLIT(32, false); }
+            else { DR_SPLIT(kStackDepth, false); }
         }
+#undef DR_SPLIT
         return;
     }
 #define DR_PRIM(S, C, X, A) k_primary<S, C, X, A><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx)
