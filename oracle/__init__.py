@@ -49,7 +49,7 @@ class _Options(C.Structure):
                 ("num_threads", C.c_int32), ("unit_mask", C.c_void_p),
                 ("dir_mode", C.c_int32), ("dir_log", C.c_void_p),
                 ("edge_pdf", C.c_void_p), ("mix", C.c_double), ("mix_terms", C.c_int32), ("aov", C.c_int32),
-                ("edge_t_mode", C.c_int32)]
+                ("edge_t_mode", C.c_int32), ("edge_candidates", C.c_int32)]
 
 
 class _Outputs(C.Structure):
@@ -73,6 +73,7 @@ def lib():
         _lib.orc_closest_hit.restype = C.c_int
         _lib.orc_edge_tree_pdf.restype = C.c_int
         _lib.orc_edge_tree_sample.restype = C.c_int
+        _lib.orc_edge_tree_select.restype = C.c_int
         _lib.orc_edge_t_cosine.restype = C.c_int
         _lib.orc_edge_t_cosine_pdf.restype = C.c_double
     return _lib
@@ -121,14 +122,17 @@ def _camera_struct(cam, keep=None, params64=None):
 def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, primary=True,
            secondary=True, use_bvh=True, exclude_flagged=False, threads=1, unit_mask=None,
            view_id=0, want_flags=False, vertices64=None, albedo64=None, camera64=None,
-           dir_mode=0, dir_log=None, edge_pdf=None, mix=0.0, mix_terms=3, edge_stats=False, aov=0, edge_t=0):
+           dir_mode=0, dir_log=None, edge_pdf=None, mix=0.0, mix_terms=3, edge_stats=False, aov=0, edge_t=0,
+           edge_candidates=0):
     """Returns a dict with image, (if d_image) d_vertices, d_albedo, d_camera,
     the matching mass arrays, unit flags and stats; with edge_stats=True also
     the per-edge harvest statistic. edge_pdf (a distribution over all edges)
     and mix in [0, 1) select the proposal mixture (mix_terms: bit 0 primary,
     bit 1 secondary). aov selects a geometry buffer instead of radiance
     (1-3 position, 4-6 shading normal, 7 albedo). edge_t = 1 draws the point
-    on each secondary edge by the clamped cosine instead of uniformly."""
+    on each secondary edge by the clamped cosine instead of uniformly.
+    edge_candidates = M > 1 selects each secondary edge by M samples
+    distributed down the hierarchy and weighted reservoir selection."""
     keep = []
     s = _scene_struct(scene, keep, vertices64, albedo64)
     c = _camera_struct(cam, keep, camera64)
@@ -141,7 +145,7 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
     q = None if edge_pdf is None else np.ascontiguousarray(edge_pdf, np.float64)
     o = _Options(spp, max_depth, seed, view_id, int(interior), int(primary), int(secondary),
                  int(use_bvh), int(exclude_flagged), threads, _ptr(mask), int(dir_mode), _ptr(dir_log),
-                 _ptr(q), float(mix), int(mix_terms), int(aov), int(edge_t))
+                 _ptr(q), float(mix), int(mix_terms), int(aov), int(edge_t), int(edge_candidates))
     res = {"image": np.zeros((Hw, Ww), np.float64), "stats": np.zeros(8, np.int64)}
     if d_image is not None:
         dimg = np.ascontiguousarray(np.broadcast_to(np.asarray(d_image, np.float64), (Hw, Ww)))
@@ -169,7 +173,8 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
 
 TIE_REASONS = ["near_miss_in_front", "equal_t_hits", "hit_near_edge", "hit_near_tmin", "grazing_hit",
                "shadow_near_edge", "shadow_near_ends", "cdf_tie", "inside_box_tie", "horizon_tie",
-               "vsphere_tie", "branch_tie", "ill_conditioned_edge", "pixel_boundary", "silhouette_sign", "mixture_component", "grazing_departure"]
+               "vsphere_tie", "branch_tie", "ill_conditioned_edge", "pixel_boundary", "silhouette_sign",
+               "mixture_component", "grazing_departure", "split_tie", "reservoir_tie"]
 
 
 def tie_reasons(reset=True):
@@ -268,6 +273,27 @@ def edge_tree_sample(scene, cam, p, n, u):
     if rc:
         raise RuntimeError(f"orc_edge_tree_sample failed {rc}")
     return edge, pdf
+
+
+def edge_tree_select(scene, cam, p, n, M, u):
+    """Stratified M-sample descent with reservoir selection from shading point
+    p with normal n: one draw per row of u (the row's uniforms used in order).
+    Returns (edge [count], weight [count]) with weight = W / (M imp) of the
+    kept edge."""
+    keep = []
+    s = _scene_struct(scene, keep)
+    c = _camera_struct(cam)
+    u = np.ascontiguousarray(u, np.float64)
+    cnt, stride = u.shape
+    edge = np.zeros(cnt, np.int32)
+    w = np.zeros(cnt, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    n = np.ascontiguousarray(n, np.float64)
+    rc = lib().orc_edge_tree_select(C.byref(s), C.byref(c), _vp(p), _vp(n), int(M), cnt, _vp(u), stride, _vp(edge),
+                                    _vp(w))
+    if rc:
+        raise RuntimeError(f"orc_edge_tree_select failed {rc}")
+    return edge, w
 
 
 def secondary_forms(p, v0, v1, t, m0, nm):

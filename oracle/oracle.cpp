@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 #include <vector>
 #ifdef _OPENMP
@@ -49,6 +50,8 @@ const double kTiePx = 1e-3;       // edge point vs. pixel boundary (pixels)
 const double kTieCond = 1e-3;     // sin(angle(v0', v1')) of secondary edges
 const double kTieBox = 1e-6;      // relative point-in-box / sphere tests
 const double kTieDepart = 1e-6;   // FP32 error of a surface point, relative to max(1, |x|) (rays leaving a surface)
+const double kTieRes = 1e-4;      // reservoir uniform vs. its FP32 keep probability (relative): weights are
+                                  // importance / descent pdf, a chain of some 25 operations per level
 
 // Constants of the estimator (shared by specification with the GPU path).
 const double kEpsPx = 1e-3;       // primary: offset of the two sides, pixels
@@ -60,7 +63,7 @@ const double kVsphereMargin = 1e-5;  // v-sphere pruning only beyond this relati
 const double kHorizon = 1e-5;     // edge points within this * diagonal of the tangent plane are skipped
 
 // Philox counter tags.
-enum : uint32_t { TAG_CAM = 0, TAG_PEDGE = 1, TAG_SEDGE = 1 };  // SEDGE_k = 1 + k
+enum : uint32_t { TAG_CAM = 0, TAG_PEDGE = 1, TAG_SEDGE = 1, TAG_SELECT = 16 };  // SEDGE_k = 1 + k, SELECT_k = 16 + k
 const int kSideBlockBase = 32;    // side-path blocks of secondary edge samples
 const int kMaxLevels = 64;
 
@@ -970,6 +973,69 @@ double tree_pdf_edge(const TreeQuery& q, int e, Unit* U) {
     return pdf;
 }
 
+// Stratified multi-sample descent with weighted reservoir selection (Ch. 5,
+// Edge selection: a number of samples start at the root and are distributed
+// to the two children of every node in proportion to their importance; one
+// edge is finally kept by weighted reservoir sampling with the leaves'
+// importance as weight).
+//
+// M samples enter at the root. The n samples that reach a node are divided
+// between its children: child 0 receives floor(n p0 + xi) of them (p0 its
+// share of the two importances, xi uniform), so each child receives n p_c in
+// expectation and a leaf e receives M pdf_e, pdf_e being the probability that
+// one descent (tree_sample) ends at e. The leaves reached form the candidates,
+// visited depth first with child 0 before child 1; a leaf holding n_e samples
+// has weight n_e imp_e / pdf_e (imp_e: its importance at its parent), and one
+// candidate z is kept by weighted reservoir sampling. In place of 1 / pdf,
+// the kept edge carries W / (M imp_z), W the total weight: resampled
+// importance sampling, whose expectation is sum_e E[n_e] f(e) / (M pdf_e) =
+// sum_e f(e). Uniforms: next_u() is called once per split and once per
+// candidate, in visiting order. Returns -1 when no leaf was reached.
+template <class NextU>
+int tree_select(const TreeQuery& q, int M, NextU&& next_u, double& weight, Unit* U) {
+    const ETree& t = *q.t;
+    double W = 0, impz = 0;
+    int z = -1;
+    auto split = [&](int n, double wl, double wr) {
+        double p0 = wl / (wl + wr);
+        double x = n * p0 + next_u();
+        if (U && p0 > 0 && p0 < 1 && std::fabs(x - std::round(x)) < kTieU * n) TIE(*U, 17);
+        return std::min(std::max((int)std::floor(x), 0), n);
+    };
+    std::function<void(int, bool, int, double, double)> child = [&](int node, bool h2, int n, double pdf,
+                                                                      double imp) {
+        if (n == 0) return;
+        const ENode& nd = t.nodes[node];
+        if (nd.edge >= 0) {
+            double om = n * imp / pdf;
+            W += om;
+            double r = om / W;
+            double u = next_u();
+            if (U && std::fabs(u - r) < kTieRes * r) TIE(*U, 18);
+            if (u < r) { z = nd.edge; impz = imp; }
+            return;
+        }
+        double wl = importance(q, t.nodes[nd.left], h2, nd.lo, nd.hi, U);
+        double wr = importance(q, t.nodes[nd.right], h2, nd.lo, nd.hi, U);
+        if (wl + wr <= 0) return;
+        int n0 = split(n, wl, wr);
+        child(nd.left, h2, n0, pdf * (wl / (wl + wr)), wl);
+        child(nd.right, h2, n - n0, pdf * (wr / (wl + wr)), wr);
+    };
+    double lo[3], hi[3];
+    root_box(t, lo, hi);
+    double w[2] = {0, 0};
+    for (int h = 0; h < 2; ++h)
+        if (t.root[h] >= 0) w[h] = importance(q, t.nodes[t.root[h]], h == 1, lo, hi, U);
+    if (w[0] + w[1] <= 0) return -1;
+    int n0 = split(M, w[0], w[1]);
+    if (t.root[0] >= 0) child(t.root[0], false, n0, w[0] / (w[0] + w[1]), w[0]);
+    if (t.root[1] >= 0) child(t.root[1], true, M - n0, w[1] / (w[0] + w[1]), w[1]);
+    if (z < 0) return -1;
+    weight = W / (M * impz);
+    return z;
+}
+
 // ---------------------------------------------------------------------------
 // Differentiation environment: vertex positions, albedos and camera as
 // tape leaves (created on first use within a unit).
@@ -1422,6 +1488,19 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                     }
                     pdf = o.mix * o.edge_pdf[ei] + (1.0 - o.mix) * pt;
                     if (!(pdf > 0)) continue;
+                } else if (o.edge_candidates > 1) {
+                    // several samples through the hierarchy, one kept: the
+                    // kept edge's weight W / (M imp) stands in for 1 / pdf
+                    Stream rs{sid, o.view_id, TAG_SELECT + (uint32_t)k, C.k0, C.k1};
+                    double sc[4];
+                    uint32_t cnt = 0;
+                    auto next_u = [&]() {
+                        if ((cnt & 3) == 0) rs.block(cnt >> 2, sc);
+                        return sc[cnt++ & 3];
+                    };
+                    double wsel = 0;
+                    ei = tree_select(q, o.edge_candidates, next_u, wsel, &U);
+                    if (ei >= 0) pdf = 1.0 / wsel;
                 } else {
                     ei = tree_sample(q, b0[0], level_u, pdf, &U, dbg);
                 }
@@ -1701,6 +1780,30 @@ int orc_edge_tree_sample(const orc_scene* sd, const orc_camera* c, const double 
     return ORC_OK;
 }
 
+int orc_edge_tree_select(const orc_scene* sd, const orc_camera* c, const double p[3], const double n[3], int32_t M,
+                         int32_t count, const double* u, int32_t ustride, int32_t* edge, double* weight) {
+    Scn s;
+    ETree t;
+    int rc = tree_setup(sd, c, s, t);
+    if (rc) return rc;
+    if (M < 1 || ustride < 1) return ORC_EINVAL;
+    TreeQuery q{&s, &t, V3d{p[0], p[1], p[2]}, V3d{n[0], n[1], n[2]}, -1};
+    for (int i = 0; i < count; ++i) {
+        const double* ui = u + (size_t)i * ustride;
+        int k = 0;
+        bool over = false;
+        auto next_u = [&]() {
+            if (k >= ustride) { over = true; return 0.5; }
+            return ui[k++];
+        };
+        double w = 0;
+        edge[i] = tree_select(q, M, next_u, w, nullptr);
+        if (over) return ORC_EINVAL;
+        weight[i] = edge[i] >= 0 ? w : 0;
+    }
+    return ORC_OK;
+}
+
 void orc_secondary_forms(const double p_[3], const double v0_[3], const double v1_[3], double t, const double m0_[3],
                          const double nm_[3], double area_form[9], double dir_form[9]) {
     V3d p{p_[0], p_[1], p_[2]}, v0{v0_[0], v0_[1], v0_[2]}, v1{v1_[0], v1_[1], v1_[2]};
@@ -1755,6 +1858,10 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
     C.s = &s; C.oc = oc; C.o = o; C.vw = &vw; C.et = need_tree ? &et : nullptr;
     bool mix = o->edge_pdf && o->mix > 0;
     if (mix && !(o->mix < 1)) return ORC_EINVAL;
+    // several samples per descent: up to 64, not with the proposal mixture
+    // (the kept edge has no closed-form probability to mix with)
+    if (o->edge_candidates < 0 || o->edge_candidates > 64) return ORC_EINVAL;
+    if (o->edge_candidates > 1 && mix && (o->mix_terms & 2)) return ORC_EINVAL;
     C.mix_p = mix && (o->mix_terms & 1);
     C.mix_s = mix && (o->mix_terms & 2) && need_tree;
     if (C.mix_p) build_view_mix(vw, o->edge_pdf, o->mix, vw);

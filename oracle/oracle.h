@@ -80,6 +80,12 @@ typedef struct {
      * proportion to the clamped cosine with the shading normal in the
      * arc-length measure of its direction (closed-form inverse). */
     int32_t edge_t_mode;
+    /* Secondary edge selection: 0 or 1 = one descent of the hierarchy, its
+     * pdf in the weight; M in 2..64 = M samples distributed down the
+     * hierarchy in proportion to importance, one of the leaves reached kept
+     * by weighted reservoir sampling (weight W / (M imp) in place of 1/pdf).
+     * Not with a secondary proposal mixture. */
+    int32_t edge_candidates;
 } orc_options;
 
 typedef struct {
@@ -128,6 +134,14 @@ int  orc_edge_tree_pdf(const orc_scene* s, const orc_camera* c, const double p[3
  * branch probabilities along each edge's root-to-leaf path). */
 int  orc_edge_tree_pdf_of(const orc_scene* s, const orc_camera* c, const double p[3],
                           const double n[3], int32_t count, const int32_t* edges, double* pdf);
+/* Stratified multi-sample descent with reservoir selection from (p, n):
+ * count draws, draw i taking its uniforms from u[i*ustride ...] in order (one
+ * per split, one per leaf reached); edge[i] = kept edge or -1, weight[i] =
+ * W / (M imp) of the kept edge (0 when none). ORC_EINVAL if a draw needs
+ * more than ustride uniforms. */
+int  orc_edge_tree_select(const orc_scene* s, const orc_camera* c, const double p[3], const double n[3],
+                          int32_t M, int32_t count, const double* u, int32_t ustride, int32_t* edge,
+                          double* weight);
 /* One descent per row of u (u[i][0] = root uniform, u[i][1..64] = level uniforms). */
 int  orc_edge_tree_sample(const orc_scene* s, const orc_camera* c, const double p[3],
                           const double n[3], int32_t count, const double* u,
