@@ -115,18 +115,16 @@ def proposal_leg(threads_note=None):
             "gain_total_ci95": res["total"]["gain_ci95"]}
 
 
-def edge_points_leg():
-    """Points on secondary edges drawn by the clamped cosine against uniform
-    points: gradient variance x backward time of the secondary term and of the
-    whole gradient (d_image = 1), 64 seeds per sampler, on 4 views of the
+def _sampler_comparison(variants):
+    """Gradient variance x backward time of the secondary term and of the whole
+    gradient (d_image = 1), 64 seeds per sampler, on 4 views of the
     1,000-triangle scene (256x256, 16 spp, depth 1) and on a 128x128 window of
-    the 81,936-triangle depth-3 scene (8 spp)."""
+    the 81,936-triangle depth-3 scene (8 spp): the default sampler against each
+    variant (keyword arguments of render_backward), with bootstrap intervals."""
     from paper_1904_12228_amd import api, proposal, scenegen
 
     out = {}
-    for name, cfg, views, depth in (
-            ("config2", scenegen.config2(), None, 1),
-            ("config3_window", scenegen.config3(), None, 3)):
+    for name, cfg, depth in (("config2", scenegen.config2(), 1), ("config3_window", scenegen.config3(), 3)):
         S = api.Scene(cfg.scene)
         if name == "config2":
             views = [(cfg.camera, 16)] + scenegen.orbit_views(77, 3, sizes=((256, 256),), spp=(16,))
@@ -134,19 +132,40 @@ def edge_points_leg():
             views = [(cfg.camera.with_window(192, 192, 320, 320), 8)]
         res = {}
         for term, terms in (("secondary", 4), ("total", 0)):
-            plain, cosine = [], []
+            base = []
             for i, (cam, spp) in enumerate(views):
                 seeds = [s + 1000 * i for s in range(64)]
                 G, ta = proposal.gradient_samples(S, cam, spp, depth, seeds, terms=terms)
-                H, tb = proposal.gradient_samples(S, cam, spp, depth, [s + 500 for s in seeds], terms=terms, edge_t=1)
-                plain.append((G, sorted(ta)[len(ta) // 2]))
-                cosine.append((H, sorted(tb)[len(tb) // 2]))
-            res[term] = proposal.variance_time_stats(plain, cosine)
+                base.append((G, sorted(ta)[len(ta) // 2]))
+            for vname, kw in variants:
+                other = []
+                for i, (cam, spp) in enumerate(views):
+                    seeds = [s + 1000 * i + 500 for s in range(64)]
+                    H, tb = proposal.gradient_samples(S, cam, spp, depth, seeds, terms=terms, **kw)
+                    other.append((H, sorted(tb)[len(tb) // 2]))
+                res.setdefault(vname, {})[term] = proposal.variance_time_stats(base, other)
+            del base
         out[name] = res
         S.close()
-        print(f"edge points: {name} done", file=sys.stderr, flush=True)
+        print(f"sampler comparison: {name} done", file=sys.stderr, flush=True)
+    return out
+
+
+def edge_points_leg():
+    """Points on secondary edges drawn by the clamped cosine against uniform
+    points (see _sampler_comparison)."""
+    res = _sampler_comparison([("cosine", {"edge_t": 1})])
     return {"metric": "gradient variance x time gain (uniform points / clamped-cosine points), 95% bootstrap "
-                      "interval", **out}
+                      "interval", **{k: v["cosine"] for k, v in res.items()}}
+
+
+def selection_leg():
+    """Secondary edges chosen by M samples down the hierarchy and weighted
+    reservoir selection (M = 4, 16) against one descent (see
+    _sampler_comparison)."""
+    res = _sampler_comparison([(f"M{m}", {"edge_candidates": m}) for m in (4, 16)])
+    return {"metric": "gradient variance x time gain (one descent / M-sample selection), 95% bootstrap interval",
+            **res}
 
 
 def gbuffer_leg(S, cam, spp, d_image, reps=3):
@@ -278,6 +297,8 @@ def main():
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal variance x time leg")
     ap.add_argument("--no-inverse", action="store_true", help="skip the batched inverse-rendering leg")
     ap.add_argument("--no-gbuffer", action="store_true", help="skip the geometry-buffer leg")
+    ap.add_argument("--no-selection", action="store_true",
+                    help="skip the multi-sample edge selection vs one descent variance x time leg")
     ap.add_argument("--no-edge-points", action="store_true",
                     help="skip the clamped-cosine vs uniform edge-point variance x time leg")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
@@ -391,6 +412,9 @@ def main():
     if not args.no_edge_points:
         print("running the edge-point sampling leg", file=sys.stderr, flush=True)
         out["edge_points"] = edge_points_leg()
+    if not args.no_selection:
+        print("running the edge-selection leg", file=sys.stderr, flush=True)
+        out["edge_selection"] = selection_leg()
     if not args.no_inverse:
         print("running the batched inverse-rendering leg", file=sys.stderr, flush=True)
         out["inverse_rendering"] = inverse_leg()

@@ -131,6 +131,18 @@ typedef struct {
      * inverse; the Lambertian case of sampling the shading lobe along the
      * edge), weighted by its density. Other values: DR_ERROR_INVALID_VALUE. */
     int32_t  edge_t_mode;
+    /* Edge chosen for each secondary edge sample (drRenderBackward only; Ch. 5,
+     * Edge selection): 0 or 1 = one descent of the edge hierarchy, weighted
+     * by its pdf; M in 2..16 = M samples distributed down the hierarchy, at
+     * every node in proportion to the children's importance (the first child
+     * receives floor(n p + xi) of the node's n samples), and one of the
+     * leaves reached kept by weighted reservoir sampling with weight
+     * n_e imp_e / pdf_e; the kept edge is weighted by W / (M imp) in place of
+     * 1/pdf (W: total weight; unbiased because a leaf receives M pdf_e
+     * samples in expectation). M > 1 needs max_depth <= 3, no secondary
+     * proposal mixture and no geometry buffer, and is not taken by batches;
+     * otherwise, or M > 16: DR_ERROR_INVALID_VALUE. */
+    int32_t  edge_candidates;
 } drRenderOptions;
 
 /* Creates a scene: validates sizes and indices (host copy of the topology),

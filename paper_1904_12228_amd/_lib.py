@@ -46,7 +46,8 @@ class RenderOptions(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("view_id", C.c_uint32), ("terms", C.c_uint32), ("unit_mask", C.c_void_p),
                 ("edge_pdf", C.c_void_p), ("edge_mix", C.c_float), ("edge_mix_terms", C.c_uint32),
-                ("edge_stats", C.c_void_p), ("aov", C.c_int32), ("edge_t_mode", C.c_int32)]
+                ("edge_stats", C.c_void_p), ("aov", C.c_int32), ("edge_t_mode", C.c_int32),
+                ("edge_candidates", C.c_int32)]
 
 
 class Profile(C.Structure):

@@ -40,10 +40,10 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 def options_struct(spp, max_depth, seed=0, view_id=0, terms=0, unit_mask=None, edge_pdf=None, edge_mix=0.0,
-                   edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0) -> _lib.RenderOptions:
+                   edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0, edge_candidates=0) -> _lib.RenderOptions:
     return _lib.RenderOptions(int(spp), int(max_depth), int(seed), int(view_id), int(terms), _ptr(unit_mask),
                               _ptr(edge_pdf), float(edge_mix), int(edge_mix_terms), _ptr(edge_stats), int(aov),
-                              int(edge_t))
+                              int(edge_t), int(edge_candidates))
 
 
 # geometry-buffer channels of drRenderOptions.aov
@@ -108,7 +108,7 @@ class Scene:
 
     def render_backward(self, cam, spp, max_depth, d_image, seed=0, view_id=0, terms=0, unit_mask=None,
                         want=("vertices", "albedo", "camera"), outs=None, edge_pdf=None, edge_mix=0.0,
-                        edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0):
+                        edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0, edge_candidates=0):
         """Gradients w.r.t. vertices [V,3], albedo [T] and camera [9]. With
         edge_pdf ([E] device distribution) and edge_mix > 0 the edge samples
         are drawn from the proposal mixture; edge_stats ([E] float32 device
@@ -130,7 +130,7 @@ class Scene:
         if edge_stats is not None:
             assert edge_stats.dtype == torch.float32 and edge_stats.is_contiguous() and edge_stats.numel() == self.num_edges
         o = options_struct(spp, max_depth, seed, view_id, terms, unit_mask, edge_pdf, edge_mix, edge_mix_terms,
-                           edge_stats, aov, edge_t)
+                           edge_stats, aov, edge_t, edge_candidates)
         _lib.check(_lib.load().drRenderBackward(self._h, C.byref(c), C.byref(o), _ptr(d_image), _ptr(dv), _ptr(da),
                                                 _ptr(dc), _stream()), "drRenderBackward")
         return dv, da, dc

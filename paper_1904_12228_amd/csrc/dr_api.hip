@@ -73,7 +73,12 @@ bool valid_options(const drRenderOptions* o) {
     return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0 &&
            o->edge_mix >= 0.0f && o->edge_mix < 1.0f &&
            (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) == 0 && o->aov >= 0 && o->aov <= 8 &&
-           (o->aov == 0 || (o->edge_mix == 0.0f && !o->edge_stats)) && (o->edge_t_mode == 0 || o->edge_t_mode == 1);
+           (o->aov == 0 || (o->edge_mix == 0.0f && !o->edge_stats)) && (o->edge_t_mode == 0 || o->edge_t_mode == 1) &&
+           o->edge_candidates >= 0 && o->edge_candidates <= kSelectMax &&
+           (o->edge_candidates <= 1 ||
+            (o->max_depth <= 3 && o->aov == 0 &&
+             !(o->edge_pdf && o->edge_mix > 0.0f &&
+               (o->edge_mix_terms == 0 || (o->edge_mix_terms & DR_TERM_SECONDARY)))));
 }
 
 ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {

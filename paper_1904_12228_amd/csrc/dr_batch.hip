@@ -101,7 +101,8 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
     for (int v = 0; v < n; ++v) {
         const drRenderOptions& o = opts[v];
         if (!valid_camera(&cams[v]) || !valid_options(&o) || !images[v] || !d_images[v]) return DR_ERROR_INVALID_VALUE;
-        if (o.max_depth != opts[0].max_depth || o.edge_pdf || o.edge_stats || o.edge_mix != 0.0f || o.aov != 0)
+        if (o.max_depth != opts[0].max_depth || o.edge_pdf || o.edge_stats || o.edge_mix != 0.0f || o.aov != 0 ||
+            o.edge_candidates > 1)
             return DR_ERROR_INVALID_VALUE;
     }
     drBatch_t* b = new drBatch_t();

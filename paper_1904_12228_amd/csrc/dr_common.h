@@ -26,6 +26,8 @@ constexpr int kStackDepth = 64;       // largest BVH traversal stack (entries pe
 constexpr int kMaxLevels = 64;        // edge-tree descent levels (16 Philox blocks x 4)
 constexpr int kSideBlockBase = 32;    // Philox block base of secondary side paths
 constexpr uint32_t kTagCam = 0, kTagPedge = 1, kTagSedge = 1;  // SEDGE_k = 1 + k
+constexpr uint32_t kTagSelect = 16;     // SELECT_k = 16 + k: uniforms of the multi-sample edge selection
+constexpr int kSelectMax = 16;          // largest number of samples of the multi-sample edge selection
 
 // ---------------------------------------------------------------------------
 // vector math

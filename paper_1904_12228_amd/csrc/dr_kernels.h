@@ -767,6 +767,119 @@ __device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int 
     return 0.0f;
 }
 
+// Stratified multi-sample descent with weighted reservoir selection (Edge
+// selection). M samples enter at the root; the n samples that reach a node are
+// divided between its children, the first receiving floor(n p0 + xi) (p0 its
+// share of the two importances, xi uniform), so a leaf e receives M pdf_e in
+// expectation, pdf_e being the probability that one descent ends there. The
+// leaves reached are visited depth first, first child first; a leaf holding
+// n_e samples has weight n_e imp_e / pdf_e (imp_e: its importance at its
+// parent) and one is kept by weighted reservoir sampling. Returns the kept
+// edge (or -1) and, in `pdf`, M imp_z / W (W: total weight), which takes the
+// place of the descent pdf in the sample's weight: resampled importance
+// sampling, unbiased since sum_e E[n_e] f(e) / (M pdf_e) = sum_e f(e).
+// Uniforms from `rs` in visiting order: one per split, one per leaf reached.
+// `stk`: this lane's first LDS word, kSelectMax entries of 4 words, strided
+// by `stride`: the deferred second children (their sample groups are
+// disjoint and non-empty, so at most M - 1 are pending).
+template <class W>
+__device__ inline int tree_select(const TreeView& tv, const TreeCtx& q, const Rng& rs, int M, float& pdf, int* stk,
+                                  int stride, W& wk) {
+    const ETNode* nodes = tv.nodes;
+    uint32_t c = 0;
+    float4 ub = make_float4(0, 0, 0, 0);
+    auto next_u = [&]() {
+        if ((c & 3) == 0) ub = rs.block(c >> 2);
+        int k = c & 3;
+        ++c;
+        return k == 0 ? ub.x : (k == 1 ? ub.y : (k == 2 ? ub.z : ub.w));
+    };
+    float Wt = 0.0f, impz = 0.0f;
+    int z = -1;
+    auto candidate = [&](int edge, int n, float pd, float imp) {
+        float om = (float)n * imp / pd;
+        Wt += om;
+        float r = om / Wt;
+        if (next_u() < r) {
+            z = edge;
+            impz = imp;
+        }
+    };
+    int sp = 0;
+    int node = 0, n = M;
+    float pd = 1.0f;
+    for (int guard = 0; guard <= M * (kMaxLevels + 1); ++guard) {
+        bool descend = false;
+        {
+            const ETNode N = load_node(nodes, node);
+            wk.tree();
+            // the node's box: the union of its children's (of the non-empty
+            // ones at the virtual root), as its parent stores it
+            float plo[3], phi[3];
+            for (int k = 0; k < 3; ++k) { plo[k] = 3e38f; phi[k] = -3e38f; }
+            for (int ci = 0; ci < 2; ++ci)
+                if (node != 0 || N.child[ci] != 0)
+                    for (int k = 0; k < 3; ++k) {
+                        plo[k] = fminf(plo[k], N.ch[ci].lo[k]);
+                        phi[k] = fmaxf(phi[k], N.ch[ci].hi[k]);
+                    }
+            int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
+            float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
+            float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
+            float tot = w0 + w1;
+            if (tot > 0.0f) {
+                float p0 = w0 / tot;
+                int n0 = min(max((int)floorf((float)n * p0 + next_u()), 0), n);
+                int n1 = n - n0;
+                if (n1 > 0) {
+                    // the second child waits until the first one's subtree is done
+                    int* e = stk + 4 * sp * stride;
+                    e[0] = N.child[1];
+                    e[stride] = n1;
+                    e[2 * stride] = __float_as_int(pd * (w1 / tot));
+                    e[3 * stride] = __float_as_int(w1);
+                    ++sp;
+                }
+                if (n0 > 0) {
+                    int ref = N.child[0];
+                    if (ref < 0) {
+                        candidate(~ref, n0, pd * p0, w0);
+                    } else {
+                        node = ref;
+                        n = n0;
+                        pd = pd * p0;
+                        descend = true;
+                    }
+                }
+            }
+        }
+        if (descend) continue;
+        // next deferred child; leaves among them are candidates at once
+        bool found = false;
+        while (sp > 0) {
+            --sp;
+            const int* e = stk + 4 * sp * stride;
+            int ref = e[0], ne = e[stride];
+            float pe = __int_as_float(e[2 * stride]), ie = __int_as_float(e[3 * stride]);
+            if (ref < 0) {
+                candidate(~ref, ne, pe, ie);
+            } else {
+                node = ref;
+                n = ne;
+                pd = pe;
+                found = true;
+                break;
+            }
+        }
+        if (!found) {
+            if (z >= 0) pdf = (float)M * impz / Wt;
+            return z;
+        }
+    }
+    atomicOr(q.s->err, kErrTreeDepth);
+    return -1;
+}
+
 // ---------------------------------------------------------------------------
 // Point on a secondary edge in proportion to the clamped cosine (Importance
 // sampling on an edge, Lambertian lobe). Seen from p the edge is a great-
@@ -1189,10 +1302,12 @@ __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArg
 // Each lane rebuilds its unit's path up to its vertex with the adjoint pass's
 // arithmetic (same operations in the same order) and appends its side-path
 // query to segment kk of the queue.
-template <int STK, bool MIX>
+template <int STK, bool MIX, bool SEL = false>
 __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
                                                      int nvert, MixArgs mx) {
-    // no rays are traced here: no traversal stack (STK only names the variant)
+    // no rays are traced here: no traversal stack (STK only names the variant);
+    // SEL: the multi-sample edge selection and its LDS stack of deferred children
+    __shared__ int sel_stk[SEL ? kSelectMax * 4 * BS : 1];
     int lane = threadIdx.x;
     NoWork wk;
     long item = (long)blockIdx.x * BS + lane;
@@ -1259,6 +1374,9 @@ __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderA
                     }
                     pdf = mx.mix * mx.q[ei] + (1.0f - mx.mix) * pt;
                     if (!(pdf > 0.0f) || s.ekind[ei] == 0) break;
+                } else if (SEL) {
+                    Rng rs{sid, a.view, kTagSelect + (uint32_t)(kk + 1), a.k0, a.k1};
+                    ei = tree_select(tv, q, rs, a.cands, pdf, sel_stk + lane, BS, wk);
                 } else {
                     ei = tree_sample(tv, q, rk, b0.x, pdf, wk, m == a.debug_unit);
                 }
@@ -1566,6 +1684,7 @@ static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions&
     a.gstride = 0;
     a.aov = o.aov;
     a.edge_t = o.edge_t_mode;
+    a.cands = o.edge_candidates;
     return a;
 }
 

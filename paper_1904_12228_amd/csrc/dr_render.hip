@@ -89,8 +89,11 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
         EvScope ev(s, 2, st);
         a.counters = cbase ? cbase + 16 : nullptr;
         dim3 g(nblk(a.M, BS));
-        // the split kernels serve the mixture up to kernel depth 3
+        // the split kernels serve the mixture up to kernel depth 3, and the
+        // multi-sample edge selection (which only they implement)
+        if (a.cands > 1) a.counters = nullptr;
         bool split = !a.counters && s->split_backward && (!use_mix || o.max_depth <= 3);
+        if (a.cands > 1 && !(split && o.max_depth <= 3)) return DR_ERROR_INVALID_VALUE;
         SplitArgs sp{};
         // queue capacity: MAXD (the kernels' template depth: 1, 3 or 6) slots per unit
         int maxd = o.max_depth <= 1 ? 1 : (o.max_depth <= 3 ? 3 : 6);

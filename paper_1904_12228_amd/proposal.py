@@ -138,7 +138,7 @@ class EdgeProposal:
 
 
 def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mix=0.0, mix_terms=0,
-                           d_image=1.0, terms=0, edge_t=0):
+                           d_image=1.0, terms=0, edge_t=0, edge_candidates=0):
     """Sum over vertex-gradient entries of the variance of the estimate across
     seeds, the mean gradient, and the mean time of one drRenderBackward (HIP
     events around the call, forward checkpoints excluded)."""
@@ -155,7 +155,8 @@ def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=No
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         scene.render_backward(cam, spp, depth, dimg, seed=sd, terms=terms, want=("vertices",), outs=(dv, None, None),
-                              edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t)
+                              edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t,
+                              edge_candidates=edge_candidates)
         e1.record(st)
         e1.synchronize()
         ms += e0.elapsed_time(e1)
@@ -169,7 +170,7 @@ def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=No
 
 
 def gradient_samples(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mix=0.0, mix_terms=0, d_image=1.0,
-                     terms=0, edge_t=0):
+                     terms=0, edge_t=0, edge_candidates=0):
     """Per-seed vertex gradients [len(seeds), 3V] (float64, device) and the
     drRenderBackward duration of each seed in ms (HIP events around the call,
     forward checkpoints excluded)."""
@@ -185,7 +186,8 @@ def gradient_samples(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mi
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         scene.render_backward(cam, spp, depth, dimg, seed=sd, terms=terms, want=("vertices",), outs=(dv, None, None),
-                              edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t)
+                              edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t,
+                              edge_candidates=edge_candidates)
         e1.record(st)
         e1.synchronize()
         ms.append(e0.elapsed_time(e1))
