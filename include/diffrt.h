@@ -45,7 +45,8 @@ typedef enum {
     DR_ERROR_INVALID_VALUE = 1,   /* bad pointer, size, index or option */
     DR_ERROR_OUT_OF_MEMORY = 2,   /* device allocation failed */
     DR_ERROR_DEVICE = 3,          /* a HIP call failed, or a sticky device error is set */
-    DR_ERROR_UNSUPPORTED = 4      /* e.g. an edge shared by more than two triangles */
+    DR_ERROR_UNSUPPORTED = 4,     /* e.g. an edge shared by more than two triangles */
+    DR_ERROR_DEGENERATE_GEOMETRY = 5  /* a triangle of zero area (no normal, never hit) */
 } drStatus;
 
 typedef struct drScene_t* drScene;
@@ -150,7 +151,9 @@ typedef struct {
  * triangle BVH (binned-SAH topology on the host, boxes on the device; with
  * the environment variable DIFFRT_BVH=lbvh a Morton-code LBVH built on the
  * device). Non-finite vertex coordinates are rejected with
- * DR_ERROR_INVALID_VALUE. Synchronises `stream`. */
+ * DR_ERROR_INVALID_VALUE, a triangle whose two edge vectors have an FP32
+ * cross product of exactly zero with DR_ERROR_DEGENERATE_GEOMETRY.
+ * Synchronises `stream`. */
 drStatus drSceneCreate(drScene* out, const drSceneDesc* desc, hipStream_t stream);
 
 /* Replaces all vertex positions ([V][3] device) and rebuilds the BVH as

@@ -1,5 +1,6 @@
 // C ABI of the gfx950 differentiable path tracer (see include/diffrt.h).
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -112,6 +113,7 @@ const char* drGetErrorString(drStatus s) {
         case DR_ERROR_OUT_OF_MEMORY: return "out of device memory";
         case DR_ERROR_DEVICE: return "device error";
         case DR_ERROR_UNSUPPORTED: return "unsupported scene";
+        case DR_ERROR_DEGENERATE_GEOMETRY: return "degenerate triangle";
     }
     return "unknown status";
 }
@@ -133,6 +135,22 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
         if (v < 0 || v >= V) return DR_ERROR_INVALID_VALUE;
     for (int t = 0; t < T; ++t)
         if (I[3 * t] == I[3 * t + 1] || I[3 * t + 1] == I[3 * t + 2] || I[3 * t] == I[3 * t + 2]) return DR_ERROR_INVALID_VALUE;
+    {
+        // zero-area triangles have no normal and are never hit: rejected
+        std::vector<float> hv(3 * (size_t)V);
+        API_CHECK(hipMemcpyAsync(hv.data(), d->vertices, sizeof(float) * hv.size(), hipMemcpyDeviceToHost, st));
+        API_CHECK(hipStreamSynchronize(st));
+        for (float x : hv)
+            if (!std::isfinite(x)) return DR_ERROR_INVALID_VALUE;
+        for (int t = 0; t < T; ++t) {
+            const float* a = &hv[3 * (size_t)I[3 * t]];
+            const float* b = &hv[3 * (size_t)I[3 * t + 1]];
+            const float* c = &hv[3 * (size_t)I[3 * t + 2]];
+            float e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+            float n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2], n2 = e1[0] * e2[1] - e1[1] * e2[0];
+            if (n0 == 0.0f && n1 == 0.0f && n2 == 0.0f) return DR_ERROR_DEGENERATE_GEOMETRY;
+        }
+    }
     // unique undirected edges, sorted by (min vertex, max vertex), faces in index order
     struct K { int a, b, f; };
     std::vector<K> ks;

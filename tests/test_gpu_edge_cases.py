@@ -87,6 +87,11 @@ def test_invalid_arguments_are_rejected():
                          np.zeros(len(idx), np.float32))
         with pytest.raises(_lib.DiffrtError):
             api.Scene(scene)
+    # a triangle of zero area (three collinear vertices)
+    v = np.array([[0, 0, 1], [1, 0, 1], [2, 0, 1], [0, 1, 1]], np.float32)
+    scene = sg.Scene(v, np.array([[0, 1, 3], [0, 1, 2]], np.int32), np.full(2, 0.5, np.float32), np.zeros(2, np.float32))
+    with pytest.raises(_lib.DiffrtError, match="degenerate"):
+        api.Scene(scene)
 
 
 def test_sah_and_morton_bvh_give_the_same_results(monkeypatch):
