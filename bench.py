@@ -397,10 +397,16 @@ def main():
                                f"{S.num_triangles} triangles, {S.num_edges} edges",
                    "width": W, "height": H, "spp": spp, "max_depth": depth,
                    "triangles": S.num_triangles, "edges": S.num_edges},
-        "roofline": {"bound": "hbm", "kernel": "k_backward (paths: secondary edges + interior adjoint + scatter)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "path backward (k_bwd_sample_v + k_side + k_bwd_adjoint: secondary edges, "
+                               "interior adjoint, scatter)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": read_traffic(args.workload),
-                     "algorithmic_bytes_per_launch": bwd_bytes},
+                     "algorithmic_bytes_per_launch": bwd_bytes,
+                     # the numerator counts measured fetches: a worse tree would raise it, so the
+                     # fetches per ray and per descent are reported beside it
+                     "bvh_nodes_per_ray": bw["bvh_nodes"] / max(bw["rays"], 1),
+                     "edge_tree_nodes_per_unit_vertex": bw["tree_nodes"] / max(units * depth, 1)},
         "kernels": kernels,
     }
     if not args.no_gbuffer:

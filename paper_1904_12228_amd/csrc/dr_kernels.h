@@ -653,20 +653,27 @@ __device__ inline TreeCtx tree_ctx(const SceneView* s, v3 p, v3 n, v3 cam, int t
     return q;
 }
 
-__device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, int h2, const float* plo, const float* phi) {
-    if (ref == 0) return 0.0f;
-    if (ref < 0) {
-        int4 e = q.s->edges[~ref];
-        if (e.z == q.tri || e.w == q.tri) return 0.0f;
-    }
-    if (h2 && vsphere_prune(c, q.p - q.cam)) return 0.0f;
-    float b = cos_bound(c.lo, c.hi, q.p, q.n, q.t1, q.t2, q.hz);
-    if (b <= 0.0f) return 0.0f;
+// Whether the shading point lies in the parent's box grown by the pad: then
+// both children get importance one. Evaluated once per node.
+__device__ inline bool in_parent(const TreeCtx& q, const float* plo, const float* phi) {
     const float pv[3] = {q.p.x, q.p.y, q.p.z};
     bool in = true;
     for (int k = 0; k < 3; ++k)
         if (pv[k] < plo[k] - q.pad || pv[k] > phi[k] + q.pad) in = false;
-    if (in) return 1.0f;
+    return in;
+}
+
+__device__ inline float importance(const TreeCtx& q, const ETChild& c, int ref, int h2, bool inpar) {
+    if (ref == 0) return 0.0f;
+    if (ref < 0) {
+        // both faces of the leaf's edge in one 8-byte load
+        const int2 f = *reinterpret_cast<const int2*>(&q.s->edges[~ref].z);
+        if ((f.x == q.tri) | (f.y == q.tri)) return 0.0f;
+    }
+    if (h2 && vsphere_prune(c, q.p - q.cam)) return 0.0f;
+    float b = cos_bound(c.lo, c.hi, q.p, q.n, q.t1, q.t2, q.hz);
+    if (b <= 0.0f) return 0.0f;
+    if (inpar) return 1.0f;
     v3 ctr = {(c.lo[0] + c.hi[0]) * 0.5f, (c.lo[1] + c.hi[1]) * 0.5f, (c.lo[2] + c.hi[2]) * 0.5f};
     v3 dc = ctr - q.p;
     return c.len * b * rsqrtf(dot(dc, dc));
@@ -704,8 +711,9 @@ __device__ inline int tree_sample(const TreeView& tv, const TreeCtx& q, const Rn
         const ETNode N = load_node(nodes, node);
         wk.tree();
         int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
-        float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
-        float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
+        bool inpar = in_parent(q, plo, phi);
+        float w0 = importance(q, N.ch[0], N.child[0], h2a, inpar);
+        float w1 = importance(q, N.ch[1], N.child[1], h2b, inpar);
         float tot = w0 + w1;
         if (!(tot > 0.0f)) return -1;
         float u;
@@ -754,8 +762,9 @@ __device__ inline float tree_pdf_edge(const TreeView& tv, const TreeCtx& q, int 
             for (int k = 0; k < 3; ++k) { plo[k] = pc.lo[k]; phi[k] = pc.hi[k]; }
         }
         int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
-        float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
-        float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
+        bool inpar = in_parent(q, plo, phi);
+        float w0 = importance(q, N.ch[0], N.child[0], h2a, inpar);
+        float w1 = importance(q, N.ch[1], N.child[1], h2b, inpar);
         float tot = w0 + w1;
         if (!(tot > 0.0f)) return 0.0f;
         pdf *= (side == 0 ? w0 : w1) / tot;
@@ -824,8 +833,9 @@ __device__ inline int tree_select(const TreeView& tv, const TreeCtx& q, const Rn
                         phi[k] = fmaxf(phi[k], N.ch[ci].hi[k]);
                     }
             int h2a = node == 0 ? 0 : N.h2, h2b = node == 0 ? 1 : N.h2;
-            float w0 = importance(q, N.ch[0], N.child[0], h2a, plo, phi);
-            float w1 = importance(q, N.ch[1], N.child[1], h2b, plo, phi);
+            bool inpar = in_parent(q, plo, phi);
+            float w0 = importance(q, N.ch[0], N.child[0], h2a, inpar);
+            float w1 = importance(q, N.ch[1], N.child[1], h2b, inpar);
             float tot = w0 + w1;
             if (tot > 0.0f) {
                 float p0 = w0 / tot;
