@@ -47,9 +47,10 @@ def compare(name, gpu, orc, mass=None, floor_rel=IMG_FLOOR, case=""):
     extra = ~in_t & (err <= tol)
     line = f"{case} {name}: {int(in_t.sum())}/{gpu.size} within rule T"
     if extra.any():
-        m = np.asarray(mass, np.float64).ravel() if mass is not None else np.ones_like(err)
-        worst = float(((err - tol_t)[extra] / np.maximum(m[extra], 1e-300)).max())
-        line += f", {int(extra.sum())} need the rounding-scale term (max (err - ruleT) / mass = {worst:.2e})"
+        # share of the allowance beyond rule T (the rounding-scale term, and the
+        # floor's excess over one FP32 ulp of the largest entry) that they use
+        used = float(((err - tol_t)[extra] / np.maximum((tol - tol_t)[extra], 1e-300)).max())
+        line += f", {int(extra.sum())} need the rounding-scale term (using at most {used:.2f} of it)"
     SUMMARY.append(line)
     bad = np.nonzero(err > tol)[0]
     if bad.size:
