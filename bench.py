@@ -379,6 +379,7 @@ def main():
         "backward_ms": bwd_ms,
         "other_ms": ms - (prof["forward_ms"] + prof["primary_ms"] + prof["backward_ms"]) / args.steps,
         "counts_per_step": counts,
+        "tree_depths": {"bvh": prof["bvh_depth"], "edge_tree": prof["edge_tree_depth"]},
     }
     out = {
         "metric": "fwd+bwd samples/s at 512^2 64spp; grad variance x time, learned vs plain edge pdf",

@@ -332,6 +332,10 @@ typedef struct {
     /* per kernel (0 forward, 1 primary edges, 2 path backward): BVH node
      * fetches, triangle fetches, edge-tree node fetches, gradient atomics, rays */
     int64_t counts[3][5];
+    /* internal nodes on the longest root-to-leaf path of the triangle BVH
+     * (it bounds a traversal's stack) and of the current view's edge
+     * hierarchy (-1 before the first backward pass) */
+    int32_t bvh_depth, edge_tree_depth;
 } drProfile;
 
 drStatus drSetProfiling(drScene scene, int32_t events, int32_t counters);

@@ -53,7 +53,8 @@ class RenderOptions(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("forward_ms", C.c_double), ("primary_ms", C.c_double), ("backward_ms", C.c_double),
                 ("forward_launches", C.c_int64), ("primary_launches", C.c_int64),
-                ("backward_launches", C.c_int64), ("counts", (C.c_int64 * 5) * 3)]
+                ("backward_launches", C.c_int64), ("counts", (C.c_int64 * 5) * 3),
+                ("bvh_depth", C.c_int32), ("edge_tree_depth", C.c_int32)]
 
 COUNT_NAMES = ["bvh_nodes", "bvh_tris", "tree_nodes", "atomics", "rays"]
 KERNELS = ["forward", "primary", "backward"]

@@ -355,6 +355,9 @@ drStatus drGetProfile(drScene s, drProfile* out, int32_t reset) {
         else if (e.kind == 1) out->primary_ms += ms;
         else out->backward_ms += ms;
     }
+    out->bvh_depth = s->bvh_depth;
+    out->edge_tree_depth = -1;
+    if (s->tree_valid && s->edepth.p) API_CHECK(hipMemcpy(&out->edge_tree_depth, s->edepth.p, sizeof(int), hipMemcpyDeviceToHost));
     out->forward_launches = s->launches[0];
     out->primary_launches = s->launches[1];
     out->backward_launches = s->launches[2];

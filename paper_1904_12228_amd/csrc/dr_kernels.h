@@ -1698,8 +1698,9 @@ static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions&
     return a;
 }
 
-// Traversal stack per lane: 32 entries when the BVH is at most 32 internal
-// nodes deep (then the stack can never overflow), 64 otherwise.
-static inline bool small_stack(const drScene_t* s) { return s->bvh_depth <= 32; }
+// Traversal stack per lane: kSmallStack entries when the BVH is at most that
+// many internal nodes deep (then the stack can never overflow: a near-first
+// descent pushes at most one entry per level), kStackDepth otherwise.
+static inline bool small_stack(const drScene_t* s) { return s->bvh_depth <= kSmallStack; }
 
 }  // namespace dr

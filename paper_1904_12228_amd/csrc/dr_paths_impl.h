@@ -43,7 +43,7 @@ void launch_paths_stack(const PathLaunch& p, hipStream_t st) {
 template <int D>
 void launch_batch_paths(bool small, int grid, const SceneView& sv, const BatchLaunch& L, float* dV, float* dA,
                         hipStream_t st) {
-    if (small) k_backward_batch<D, 32><<<grid, BS, 0, st>>>(sv, L, dV, dA);
+    if (small) k_backward_batch<D, kSmallStack><<<grid, BS, 0, st>>>(sv, L, dV, dA);
     else k_backward_batch<D, kStackDepth><<<grid, BS, 0, st>>>(sv, L, dV, dA);
 }
 

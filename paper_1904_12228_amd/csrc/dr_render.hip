@@ -11,7 +11,7 @@ drStatus launch_backward(drScene_t* s, const Cam& cam, const drRenderOptions& o,
     RenderArgs a = make_args(s, cam, o);
     SceneView sv = s->view();
     bool sm = small_stack(s);
-    sv.stk_cap = sm ? 32 : kStackDepth;
+    sv.stk_cap = sm ? kSmallStack : kStackDepth;
     // gradients accumulate into `shards` copies (layout per copy: dV [3V] then
     // dA [T]), camera accumulators into `shards` x 12 floats; the copies are
     // summed into the caller's arrays at the end
@@ -77,7 +77,7 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
         EvScope ev(s, 2, st);
         a.counters = nullptr;
         dim3 g(nblk(a.M, BS)), b(BS);
-        if (sm) k_backward<1, 32, false, false, true><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx);
+        if (sm) k_backward<1, kSmallStack, false, false, true><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx);
         else k_backward<1, kStackDepth, false, false, true><<<g, b, 0, st>>>(sv, cam, a, tv, d_image, dV, dA, camacc, mx);
     } else if (o.max_depth >= 1) {
         TreeView tv;
@@ -113,17 +113,17 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
             sp.count = s->scount.as<int>();
             k_fill_count<<<1, 64, 0, st>>>(sp.count, maxd);
         }
-        int side_grid = std::max(1, std::min(nblk((long)a.M, BS), kQueueBlocks));
+        int side_grid = std::max(1, std::min(nblk((long)a.M, BS), kSideBlocks));
 PathLaunch pl{Variant{false, use_mix, a.counters != nullptr, sm}, split, g, side_grid, o.max_depth, sv, cam, a,
                       tv, sp, d_image, dV, dA, camacc, mx};
         if (o.max_depth <= 1) {
-            if (sm) launch_paths_stack<1, 32>(pl, st);
+            if (sm) launch_paths_stack<1, kSmallStack>(pl, st);
             else launch_paths_stack<1, kStackDepth>(pl, st);
         } else if (o.max_depth <= 3) {
-            if (sm) launch_paths_stack<3, 32>(pl, st);
+            if (sm) launch_paths_stack<3, kSmallStack>(pl, st);
             else launch_paths_stack<3, kStackDepth>(pl, st);
         } else {
-            if (sm) launch_paths_stack<6, 32>(pl, st);
+            if (sm) launch_paths_stack<6, kSmallStack>(pl, st);
             else launch_paths_stack<6, kStackDepth>(pl, st);
         }
     }

@@ -12,14 +12,14 @@ static int batch_grid(const BatchLaunch& L, int ctas) {
 drStatus launch_batch_forward(drScene_t* s, BatchLaunch L, int ctas, int max_pixels, hipStream_t st) {
     SceneView sv = s->view();
     bool sm = small_stack(s);
-    sv.stk_cap = sm ? 32 : kStackDepth;
+    sv.stk_cap = sm ? kSmallStack : kStackDepth;
     dim3 zg(std::max(1, std::min((max_pixels + 255) / 256, 1024)), L.nviews);
     k_batch_zero<<<zg, 256, 0, st>>>(L.views, L.nviews, 1, L.gshards);
     if (L.total == 0) return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
     if (!(ctas > 0)) L.queue = nullptr;
     else k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
     int grid = batch_grid(L, ctas);
-    if (sm) k_forward_batch<32><<<grid, BS, 0, st>>>(sv, L);
+    if (sm) k_forward_batch<kSmallStack><<<grid, BS, 0, st>>>(sv, L);
     else k_forward_batch<kStackDepth><<<grid, BS, 0, st>>>(sv, L);
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
@@ -28,7 +28,7 @@ drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth,
                                float* d_albedo, float* d_cameras, hipStream_t st) {
     SceneView sv = s->view();
     bool sm = small_stack(s);
-    sv.stk_cap = sm ? 32 : kStackDepth;
+    sv.stk_cap = sm ? kSmallStack : kStackDepth;
     // `shard`: gshards copies of [dV (3V) | dA (T)], gstride = 3V + T floats apart
     float* dV = shard;
     float* dA = shard + 3L * s->V;
@@ -39,7 +39,7 @@ drStatus launch_batch_backward(drScene_t* s, BatchLaunch L, int ctas, int depth,
         int grid = batch_grid(L, ctas);
         if (s->E > 0) {
             if (L.queue) k_fill_i32<<<1, 1, 0, st>>>(L.queue, 0);
-            if (sm) k_primary_batch<32><<<grid, BS, 0, st>>>(sv, L, dV);
+            if (sm) k_primary_batch<kSmallStack><<<grid, BS, 0, st>>>(sv, L, dV);
             else k_primary_batch<kStackDepth><<<grid, BS, 0, st>>>(sv, L, dV);
         }
         if (depth >= 1) {

@@ -15,10 +15,10 @@ void launch_primary_kernel(const Variant& v, dim3 g, const SceneView& sv, const 
     k_prim_sample<S, X><<<g, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, mx);                                          \
     k_prim_paths<S, X><<<paths_grid, b, 0, st>>>(sv, cam, a, pe, pc, pq, pcount, d_image, dV, camacc, mx)
         if (v.mix) {
-            if (v.small) { DR_SPLIT(32, true); }
+            if (v.small) { DR_SPLIT(kSmallStack, true); }
             else { DR_SPLIT(kStackDepth, true); }
         } else {
-            if (v.small) { DR_SPLIT(32, false); }
+            if (v.small) { DR_SPLIT(kSmallStack, false); }
             else { DR_SPLIT(kStackDepth, false); }
         }
 #undef DR_SPLIT
@@ -26,16 +26,16 @@ void launch_primary_kernel(const Variant& v, dim3 g, const SceneView& sv, const 
     }
 #define DR_PRIM(S, C, X, A) k_primary<S, C, X, A><<<g, b, 0, st>>>(sv, cam, a, pe, pc, d_image, dV, camacc, mx)
     if (v.aov) {
-        if (v.small) DR_PRIM(32, false, false, true);
+        if (v.small) DR_PRIM(kSmallStack, false, false, true);
         else DR_PRIM(kStackDepth, false, false, true);
     } else if (v.mix) {
-        if (v.small) DR_PRIM(32, false, true, false);
+        if (v.small) DR_PRIM(kSmallStack, false, true, false);
         else DR_PRIM(kStackDepth, false, true, false);
     } else if (v.counters) {
-        if (v.small) DR_PRIM(32, true, false, false);
+        if (v.small) DR_PRIM(kSmallStack, true, false, false);
         else DR_PRIM(kStackDepth, true, false, false);
     } else {
-        if (v.small) DR_PRIM(32, false, false, false);
+        if (v.small) DR_PRIM(kSmallStack, false, false, false);
         else DR_PRIM(kStackDepth, false, false, false);
     }
 #undef DR_PRIM
