@@ -21,8 +21,8 @@ constexpr float kVsphereMargin = 1e-5f;  // v-sphere pruning only beyond this re
 constexpr float kPi = 3.14159265358979323846f;
 constexpr int kMaxDepth = 6;
 constexpr int kMaxTriangles = 1 << 26;  // 64 B tree nodes and 48 B triangle records stay below 4 GiB
-constexpr int kQueueBlocks = 8192;      // persistent grid of the primary-path kernel (two rounds of 4,096 resident)
-constexpr int kSideBlocks = 10240;      // persistent grid of the side-path kernel (two rounds of 5,120 resident)
+constexpr int kQueueBlocks = 10240;     // persistent grid of the kernels that drain a work queue: two rounds of
+                                        // the 5,120 one-wave blocks resident at five waves per SIMD
 constexpr int kSmallStack = 24;        // short traversal stack (entries per lane), for BVHs at most 24 deep:
                                         // 6 KB of LDS per one-wave block
 constexpr int kStackDepth = 64;       // largest BVH traversal stack (entries per lane)

@@ -525,9 +525,10 @@ __global__ __launch_bounds__(BS) void k_prim_sample(SceneView s, Cam k, RenderAr
 // camera paths from their first hits (same random numbers), the jump, and
 // the endpoint and camera gradients (lanes drawing the same edge summed in
 // the wave before the atomics). MIX: the learned-proposal mixture's edge
-// choice and, when asked, the per-edge harvest statistic.
+// choice and, when asked, the per-edge harvest statistic. Five waves per SIMD
+// (at most 96 VGPRs, some spilled) measured faster than four.
 template <int STK, bool MIX>
-__global__ __launch_bounds__(BS, 4) void k_prim_paths(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
+__global__ __launch_bounds__(BS, 5) void k_prim_paths(SceneView s, Cam k, RenderArgs a, const PEdge* __restrict__ pe,
                                                    const double* __restrict__ cdf, const int3* __restrict__ q,
                                                    const int* __restrict__ count, const float* __restrict__ d_image,
                                                    float* __restrict__ dV, float* __restrict__ camacc, MixArgs mx) {

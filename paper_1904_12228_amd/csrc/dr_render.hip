@@ -63,9 +63,9 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
             pq = s->pq.as<int3>();
             pcount = s->pcount.as<int>();
         }
-        // persistent grids of the queue kernels: 8,192 blocks (two rounds of
-        // the 4,096 the device holds at once) measured best; 5,120 leaves a
-        // second round a quarter full
+        // persistent grid of the queue kernel: two rounds of the blocks the
+        // device holds at once (a grid between one and two rounds leaves the
+        // second round partly empty)
         int paths_grid = std::max(1, std::min(nblk((long)a.M, BS), kQueueBlocks));
         launch_primary_kernel(v, g, sv, cam, a, pe, pc, d_image, dV, camacc, mx, pq, pcount, paths_grid, st);
     }
@@ -113,7 +113,7 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
             sp.count = s->scount.as<int>();
             k_fill_count<<<1, 64, 0, st>>>(sp.count, maxd);
         }
-        int side_grid = std::max(1, std::min(nblk((long)a.M, BS), kSideBlocks));
+        int side_grid = std::max(1, std::min(nblk((long)a.M, BS), kQueueBlocks));
 PathLaunch pl{Variant{false, use_mix, a.counters != nullptr, sm}, split, g, side_grid, o.max_depth, sv, cam, a,
                       tv, sp, d_image, dV, dA, camacc, mx};
         if (o.max_depth <= 1) {
