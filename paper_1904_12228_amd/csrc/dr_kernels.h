@@ -137,8 +137,10 @@ __device__ __forceinline__ void forward_body(const SceneView& s, const Cam& k, c
     }
 }
 
+// Six waves per SIMD (at most 80 VGPRs, a few spilled) measured faster than
+// five; the side-path and edge-sampling kernels lose more to their spills.
 template <int STK, bool CNT>
-__global__ __launch_bounds__(BS) void k_forward(SceneView s, Cam k, RenderArgs a, float* __restrict__ image, int reduce) {
+__global__ __launch_bounds__(BS, 6) void k_forward(SceneView s, Cam k, RenderArgs a, float* __restrict__ image, int reduce) {
     __shared__ int stk[STK * BS];
     forward_body<STK, CNT>(s, k, a, image, reduce, blockIdx.x * BS, stk);
 }
