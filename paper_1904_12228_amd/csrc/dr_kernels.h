@@ -1502,23 +1502,39 @@ __device__ inline void cam_finalize(const Cam& k, const float* __restrict__ acc,
     d_camera[6] = gup.x; d_camera[7] = gup.y; d_camera[8] = gup.z;
 }
 
+// One wave: lane j sums copies j, j + 64, ...; the wave then adds the lanes.
 static __global__ void k_cam_finalize(Cam k, const float* __restrict__ acc, int shards, float* __restrict__ d_camera) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
     float sum[12];
     for (int i = 0; i < 12; ++i) {
-        sum[i] = 0.0f;
-        for (int h = 0; h < shards; ++h) sum[i] += acc[12 * h + i];
+        float v = 0.0f;
+        for (int h = threadIdx.x; h < shards; h += BS) v += acc[12 * h + i];
+        sum[i] = wave_sum(v);
     }
-    cam_finalize(k, sum, d_camera);
+    if (threadIdx.x == 0) cam_finalize(k, sum, d_camera);
 }
 
-// out[i] = sum over the copies of shard[h * stride + i], i < n
-static __global__ void k_reduce_shards(const float* __restrict__ shard, int shards, long stride, long n, float* __restrict__ out) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// out[i] = sum over the copies of shard[h * stride + i], i < n. A block of
+// 256 threads takes 32 consecutive entries: eight groups of 32 lanes read
+// copies g, g + 8, ... of them (coalesced within a group), and the eight
+// partial sums meet in LDS, so that small arrays still spread over many waves.
+// Launch with 256 threads and ceil(n / 32) blocks.
+constexpr int kReduceEntries = 32;
+static __global__ __launch_bounds__(256) void k_reduce_shards(const float* __restrict__ shard, int shards, long stride,
+                                                            long n, float* __restrict__ out) {
+    __shared__ float part[256];
+    int e = threadIdx.x % kReduceEntries, g = threadIdx.x / kReduceEntries;
+    long i = (long)blockIdx.x * kReduceEntries + e;
     float v = 0.0f;
-    for (int h = 0; h < shards; ++h) v += shard[h * stride + i];
-    out[i] = v;
+    if (i < n)
+        for (int h = g; h < shards; h += 256 / kReduceEntries) v += shard[h * stride + i];
+    part[threadIdx.x] = v;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        float t = 0.0f;
+        for (int k = 0; k < 256 / kReduceEntries; ++k) t += part[k * kReduceEntries + e];
+        out[i] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -9,7 +9,7 @@
 namespace dr {
 
 // Variant switches of one launch: geometry buffer, learned-proposal mixture,
-// work counters, 32-entry traversal stack.
+// work counters, short (kSmallStack-entry) traversal stack.
 struct Variant {
     bool aov, mix, counters, small;
 };

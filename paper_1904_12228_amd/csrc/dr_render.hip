@@ -127,10 +127,10 @@ PathLaunch pl{Variant{false, use_mix, a.counters != nullptr, sm}, split, g, side
             else launch_paths_stack<6, kStackDepth>(pl, st);
         }
     }
-    if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, shards, stride, 3L * s->V, d_vertices);
-    if (d_albedo) k_reduce_shards<<<nblk(s->T, 256), 256, 0, st>>>(dA, shards, stride, s->T, d_albedo);
+    if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, kReduceEntries), 256, 0, st>>>(dV, shards, stride, 3L * s->V, d_vertices);
+    if (d_albedo) k_reduce_shards<<<nblk(s->T, kReduceEntries), 256, 0, st>>>(dA, shards, stride, s->T, d_albedo);
     if (d_camera)
-        k_cam_finalize<<<1, 1, 0, st>>>(cam, camacc, shards, d_camera);
+        k_cam_finalize<<<1, BS, 0, st>>>(cam, camacc, shards, d_camera);
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
 

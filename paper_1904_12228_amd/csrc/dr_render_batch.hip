@@ -49,8 +49,8 @@ if (depth <= 1) launch_batch_paths<1>(sm, grid, sv, L, dV, dA, st);
             else launch_batch_paths<6>(sm, grid, sv, L, dV, dA, st);
         }
     }
-    if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, 256), 256, 0, st>>>(dV, L.gshards, L.gstride, 3L * s->V, d_vertices);
-    if (d_albedo) k_reduce_shards<<<nblk(s->T, 256), 256, 0, st>>>(dA, L.gshards, L.gstride, s->T, d_albedo);
+    if (d_vertices) k_reduce_shards<<<nblk(3L * s->V, kReduceEntries), 256, 0, st>>>(dV, L.gshards, L.gstride, 3L * s->V, d_vertices);
+    if (d_albedo) k_reduce_shards<<<nblk(s->T, kReduceEntries), 256, 0, st>>>(dA, L.gshards, L.gstride, s->T, d_albedo);
     if (d_cameras) k_cam_finalize_batch<<<(L.nviews + 63) / 64, 64, 0, st>>>(L.views, L.nviews, L.gshards, d_cameras);
     return hipGetLastError() == hipSuccess ? DR_SUCCESS : DR_ERROR_DEVICE;
 }
