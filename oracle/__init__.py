@@ -49,7 +49,8 @@ class _Options(C.Structure):
                 ("num_threads", C.c_int32), ("unit_mask", C.c_void_p),
                 ("dir_mode", C.c_int32), ("dir_log", C.c_void_p),
                 ("edge_pdf", C.c_void_p), ("mix", C.c_double), ("mix_terms", C.c_int32), ("aov", C.c_int32),
-                ("edge_t_mode", C.c_int32), ("edge_candidates", C.c_int32)]
+                ("edge_t_mode", C.c_int32), ("edge_candidates", C.c_int32),
+                ("enee", C.c_double), ("enee_width", C.c_double)]
 
 
 class _Outputs(C.Structure):
@@ -76,6 +77,10 @@ def lib():
         _lib.orc_edge_tree_select.restype = C.c_int
         _lib.orc_edge_t_cosine.restype = C.c_int
         _lib.orc_edge_t_cosine_pdf.restype = C.c_double
+        _lib.orc_edge_nee_width.restype = C.c_double
+        _lib.orc_edge_nee_sample.restype = C.c_int
+        _lib.orc_edge_nee_pdf.restype = C.c_int
+        _lib.orc_edge_nee_mix_sample.restype = C.c_int
     return _lib
 
 
@@ -123,7 +128,7 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
            secondary=True, use_bvh=True, exclude_flagged=False, threads=1, unit_mask=None,
            view_id=0, want_flags=False, vertices64=None, albedo64=None, camera64=None,
            dir_mode=0, dir_log=None, edge_pdf=None, mix=0.0, mix_terms=3, edge_stats=False, aov=0, edge_t=0,
-           edge_candidates=0):
+           edge_candidates=0, enee=0.0, enee_width=0.0):
     """Returns a dict with image, (if d_image) d_vertices, d_albedo, d_camera,
     the matching mass arrays, unit flags and stats; with edge_stats=True also
     the per-edge harvest statistic. edge_pdf (a distribution over all edges)
@@ -132,7 +137,10 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
     (1-3 position, 4-6 shading normal, 7 albedo). edge_t = 1 draws the point
     on each secondary edge by the clamped cosine instead of uniformly.
     edge_candidates = M > 1 selects each secondary edge by M samples
-    distributed down the hierarchy and weighted reservoir selection."""
+    distributed down the hierarchy and weighted reservoir selection.
+    enee = alpha in (0, 1) mixes the billboard strategy (next event
+    estimation for edges) into the secondary edge sample with probability
+    alpha; enee_width is the billboard width (0: the scene's default)."""
     keep = []
     s = _scene_struct(scene, keep, vertices64, albedo64)
     c = _camera_struct(cam, keep, camera64)
@@ -145,7 +153,8 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
     q = None if edge_pdf is None else np.ascontiguousarray(edge_pdf, np.float64)
     o = _Options(spp, max_depth, seed, view_id, int(interior), int(primary), int(secondary),
                  int(use_bvh), int(exclude_flagged), threads, _ptr(mask), int(dir_mode), _ptr(dir_log),
-                 _ptr(q), float(mix), int(mix_terms), int(aov), int(edge_t), int(edge_candidates))
+                 _ptr(q), float(mix), int(mix_terms), int(aov), int(edge_t), int(edge_candidates),
+                 float(enee), float(enee_width))
     res = {"image": np.zeros((Hw, Ww), np.float64), "stats": np.zeros(8, np.int64)}
     if d_image is not None:
         dimg = np.ascontiguousarray(np.broadcast_to(np.asarray(d_image, np.float64), (Hw, Ww)))
@@ -174,11 +183,12 @@ def render(scene, cam, spp, max_depth, seed=0, d_image=None, *, interior=True, p
 TIE_REASONS = ["near_miss_in_front", "equal_t_hits", "hit_near_edge", "hit_near_tmin", "grazing_hit",
                "shadow_near_edge", "shadow_near_ends", "cdf_tie", "inside_box_tie", "horizon_tie",
                "vsphere_tie", "branch_tie", "ill_conditioned_edge", "pixel_boundary", "silhouette_sign",
-               "mixture_component", "grazing_departure", "split_tie", "reservoir_tie"]
+               "mixture_component", "grazing_departure", "split_tie", "reservoir_tie", "billboard_crossing",
+               "billboard_race", "billboard_light_hit", "billboard_strategy"]
 
 
 def tie_reasons(reset=True):
-    out = np.zeros(20, np.int64)
+    out = np.zeros(24, np.int64)
     lib().orc_tie_reasons(_vp(out), int(reset))
     return {k: int(v) for k, v in zip(TIE_REASONS, out) if v}
 
@@ -319,3 +329,69 @@ def edge_t_cosine(p, n, v0, v1, u):
 def edge_t_cosine_pdf(p, n, v0, v1, t):
     args = [np.ascontiguousarray(x, np.float64) for x in (p, n, v0, v1)]
     return float(lib().orc_edge_t_cosine_pdf(*[_vp(a) for a in args], C.c_double(t)))
+
+
+def edge_nee_width(scene):
+    """Default billboard width of next event estimation for edges: the L2 norm
+    over the coordinates of 2% of the vertex positions' mean absolute deviation."""
+    keep = []
+    s = _scene_struct(scene, keep)
+    w = lib().orc_edge_nee_width(C.byref(s))
+    if not w >= 0:
+        raise RuntimeError("orc_edge_nee_width failed")
+    return float(w)
+
+
+def _nee_point(p, n):
+    return (np.ascontiguousarray(p, np.float64), np.ascontiguousarray(n, np.float64))
+
+
+def edge_nee_sample(scene, p, n, tri, width, count, seed=0):
+    """count draws of the billboard strategy at (p, n) on triangle tri (-1:
+    none): (edge or -1, t, s, near-tie flags)."""
+    keep = []
+    s = _scene_struct(scene, keep)
+    p, n = _nee_point(p, n)
+    e = np.zeros(count, np.int32)
+    t = np.zeros(count)
+    sv = np.zeros(count)
+    fl = np.zeros(count, np.uint8)
+    rc = lib().orc_edge_nee_sample(C.byref(s), _vp(p), _vp(n), int(tri), C.c_double(width), int(count),
+                                   C.c_uint64(seed), _vp(e), _vp(t), _vp(sv), _vp(fl))
+    if rc:
+        raise RuntimeError(f"orc_edge_nee_sample failed with code {rc}")
+    return e, t, sv, fl.astype(bool)
+
+
+def edge_nee_pdf(scene, p, n, tri, width, edges, t, sv):
+    """Density of the billboard strategy in dt ds at the given (edge, t, s)."""
+    keep = []
+    s = _scene_struct(scene, keep)
+    p, n = _nee_point(p, n)
+    e = np.ascontiguousarray(edges, np.int32)
+    t = np.ascontiguousarray(t, np.float64)
+    sv = np.ascontiguousarray(sv, np.float64)
+    out = np.zeros(len(e))
+    rc = lib().orc_edge_nee_pdf(C.byref(s), _vp(p), _vp(n), int(tri), C.c_double(width), len(e), _vp(e), _vp(t),
+                                _vp(sv), _vp(out))
+    if rc:
+        raise RuntimeError(f"orc_edge_nee_pdf failed with code {rc}")
+    return out
+
+
+def edge_nee_mix_sample(scene, cam, p, n, tri, width, alpha, count, seed=0):
+    """count draws of the mixture of the billboard strategy (probability
+    alpha) and the edge hierarchy of camera cam: (edge or -1, t, mixture
+    density in (e, t))."""
+    keep = []
+    s = _scene_struct(scene, keep)
+    c = _camera_struct(cam, keep)
+    p, n = _nee_point(p, n)
+    e = np.zeros(count, np.int32)
+    t = np.zeros(count)
+    pdf = np.zeros(count)
+    rc = lib().orc_edge_nee_mix_sample(C.byref(s), C.byref(c), _vp(p), _vp(n), int(tri), C.c_double(width),
+                                       C.c_double(alpha), int(count), C.c_uint64(seed), _vp(e), _vp(t), _vp(pdf))
+    if rc:
+        raise RuntimeError(f"orc_edge_nee_mix_sample failed with code {rc}")
+    return e, t, pdf

@@ -63,7 +63,8 @@ const double kVsphereMargin = 1e-5;  // v-sphere pruning only beyond this relati
 const double kHorizon = 1e-5;     // edge points within this * diagonal of the tangent plane are skipped
 
 // Philox counter tags.
-enum : uint32_t { TAG_CAM = 0, TAG_PEDGE = 1, TAG_SEDGE = 1, TAG_SELECT = 16 };  // SEDGE_k = 1 + k, SELECT_k = 16 + k
+// SEDGE_k = 1 + k, SELECT_k = 16 + k, ENEE_k = 32 + k (billboard strategy of the secondary edge sample)
+enum : uint32_t { TAG_CAM = 0, TAG_PEDGE = 1, TAG_SEDGE = 1, TAG_SELECT = 16, TAG_ENEE = 32 };
 const int kSideBlockBase = 32;    // side-path blocks of secondary edge samples
 const int kMaxLevels = 64;
 
@@ -330,7 +331,7 @@ int prepare(const orc_scene* d, Scn& s) {
 // Ray casting with near-tie detection
 // ---------------------------------------------------------------------------
 // Per-reason counters of near-tie flags (diagnostics for the tests).
-int64_t g_reason[20];
+int64_t g_reason[24];
 #define TIE(U, r) do { (U).flag = true; __atomic_add_fetch(&g_reason[r], 1, __ATOMIC_RELAXED); } while (0)
 
 struct Unit {
@@ -1358,6 +1359,267 @@ double cosine_edge_pdf(V3d p, V3d n, V3d pa, V3d pb, double t, double T) {
 }
 
 // ---------------------------------------------------------------------------
+// Next event estimation for edges (Ch. 5, Next event estimation for edges).
+//
+// A second strategy for the secondary edge sample at a shading point x: a
+// light point y is drawn as for next-event estimation, every edge is widened
+// into a billboard facing x, and among the billboards the segment x -> y
+// crosses one is chosen in proportion to the edge's importance; the crossing,
+// projected onto the edge, is the sample. Readings (the thesis gives the
+// construction, not its density):
+//  * the billboard of edge (pa, pb) seen from x is the planar strip
+//    { pa + t a + s v : t in [0, 1], |s| <= w/2 }, a = pb - pa, v the unit
+//    vector orthogonal to the edge and to pa - x. Its plane contains the edge
+//    and its normal points along the perpendicular from the edge's line to x,
+//    so it faces every ray leaving x; a crossing at (t, s) projects onto the
+//    edge point of parameter t;
+//  * w is the strip's full width, the L2 norm over the three coordinates of
+//    2% of the mean absolute deviation of the scene's vertex positions;
+//  * the light point is drawn afresh (the same light distribution as the
+//    forward pass's next-event estimation: a light triangle by area, a
+//    uniform point in it), and light points behind x's tangent plane or, for
+//    one-sided emitters, on an emitter's back are not used;
+//  * the importance of an edge is that of a leaf of the edge hierarchy
+//    without the parent-box rule: length x cosine bound of its box / distance
+//    of the box centre, zero for x's own triangle's edges and for edges that
+//    are not discontinuities as seen from x; the choice among the crossed
+//    billboards is an exponential race (edge e's key -log(1 - u_e) / imp_e
+//    with u_e its own uniform, the smallest key wins), which picks e with
+//    probability imp_e / sum of the crossed importances in any visiting order;
+//  * the strategy is combined with the hierarchy by one-sample multiple
+//    importance sampling: with probability alpha the billboard strategy,
+//    otherwise the hierarchy (plus a uniform s across the strip), every sample
+//    weighted by the balance-heuristic mixture density
+//    alpha p_N(e, t, s) + (1 - alpha) p_H(e) / w in the space (e, t, s). Since
+//    the integrand does not depend on s, dividing by 1/w turns that into the
+//    density alpha w p_N + (1 - alpha) p_H in (e, t) that the estimator uses.
+//
+// The density of the billboard strategy at (e, t, s): the ray from x through
+// b = pa + t a + s v meets the lights at points y = x + mu (b - x), mu > 1;
+// each such y was drawn with area density 1 / A_lights, the map from light
+// area to strip area has Jacobian |y - x|^2 cos_b / (|b - x|^2 cos_y), the
+// strip's area element is |a| dt ds, and e was chosen among the billboards
+// crossed by x -> y with probability imp_e / sum_crossed imp:
+//   p_N = |a| / A_lights * sum_y mu^2 |cos_b| / |cos_y| * imp_e / sum_crossed(x, y) imp.
+// ---------------------------------------------------------------------------
+const double kNeeMadFrac = 0.02;  // billboard width: this fraction of the mean absolute deviation
+const double kTieBB = 1e-4;       // crossing parameters vs. the strip's borders (t, and s relative to w)
+const double kTieRace = 1e-4;     // relative gap between the two smallest race keys
+const double kTieLight = 1e-4;    // barycentric margin of a light hit, relative distance of the light to b
+
+double nee_width_default(const Scn& s) {
+    double mean[3] = {0, 0, 0}, mad[3] = {0, 0, 0};
+    for (int v = 0; v < s.V; ++v)
+        for (int k = 0; k < 3; ++k) mean[k] += s.P[3 * v + k];
+    for (int k = 0; k < 3; ++k) mean[k] /= s.V;
+    for (int v = 0; v < s.V; ++v)
+        for (int k = 0; k < 3; ++k) mad[k] += std::fabs(s.P[3 * v + k] - mean[k]);
+    double w2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        double m = kNeeMadFrac * mad[k] / s.V;
+        w2 += m * m;
+    }
+    return std::sqrt(w2);
+}
+
+struct Billboard {
+    V3d pa, ah, v, nb;   // edge start, unit edge direction, unit width direction, unit normal
+    double L;            // edge length
+    bool ok;
+};
+
+Billboard billboard(const Scn& s, const Edge& e, const V3d& x) {
+    Billboard B;
+    B.pa = s.p(e.va);
+    V3d a = s.p(e.vb) - B.pa;
+    B.L = length(a);
+    B.ok = false;
+    if (!(B.L > 0)) return B;
+    B.ah = a / B.L;
+    V3d c = cross(B.ah, B.pa - x);
+    double cl = length(c);
+    if (!(cl > 0)) return B;
+    B.v = c / cl;
+    B.nb = cross(B.ah, B.v);
+    B.ok = true;
+    return B;
+}
+
+// Crossing of the segment x -> y (excluding both ends) with the strip of
+// width w; (t, sv) the crossing's strip coordinates; *near: one of the three
+// tests was within rounding of its border.
+bool bb_cross(const Billboard& B, const V3d& x, const V3d& y, double w, double& t, double& sv, bool* near) {
+    *near = false;
+    if (!B.ok) return false;
+    V3d d = y - x;
+    double den = dot(d, B.nb);
+    if (den == 0) return false;
+    double lam = dot(B.pa - x, B.nb) / den;
+    V3d r = x + d * lam - B.pa;
+    t = dot(r, B.ah) / B.L;
+    sv = dot(r, B.v);
+    bool in_t = t >= 0 && t <= 1, in_s = std::fabs(sv) <= 0.5 * w, in_l = lam > 0 && lam < 1;
+    if (in_l && in_s && (std::fabs(t) < kTieBB || std::fabs(t - 1) < kTieBB)) *near = true;
+    if (in_l && in_t && std::fabs(std::fabs(sv) - 0.5 * w) < kTieBB * w) *near = true;
+    if (in_t && in_s && std::fabs(lam - 1) < kTieLight) *near = true;
+    return in_t && in_s && in_l;
+}
+
+// Importance of edge ei at (p, n) on triangle tri (a hierarchy leaf's, no
+// parent-box rule). Edges of emitters are left to the hierarchy: their strips
+// reach the light's own plane, where the segment to a light point ends.
+double nee_importance(const Scn& s, int ei, const V3d& p, const V3d& n, int tri, Unit* U) {
+    const Edge& e = s.edges[ei];
+    if (e.kind == 0 || (tri >= 0 && (e.f0 == tri || e.f1 == tri))) return 0;
+    if (s.emi[e.f0] > 0 || (e.f1 >= 0 && s.emi[e.f1] > 0)) return 0;
+    if (!disc_from(s, e, p, U ? &U->flag : nullptr)) return 0;
+    V3d a = s.p(e.va), b = s.p(e.vb);
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) { lo[k] = std::min(comp(a, k), comp(b, k)); hi[k] = std::max(comp(a, k), comp(b, k)); }
+    double cb = cos_bound(lo, hi, p, n, U, s.diag);
+    if (cb <= 0) return 0;
+    return length(b - a) * cb / length((a + b) * 0.5 - p);
+}
+
+struct NeeQuery {
+    const Scn* s;
+    V3d p, n;
+    int tri;
+    double w;
+};
+
+// Whether x -> y crosses edge ei's strip, and the edge's importance. Near
+// ties are flagged only for edges at or near a crossing, and crossing ties
+// only for edges of positive importance: only those decisions change a result.
+bool nee_cross(const NeeQuery& q, int ei, const V3d& y, double& t, double& sv, double& imp, Unit* U) {
+    bool near;
+    bool c = bb_cross(billboard(*q.s, q.s->edges[ei], q.p), q.p, y, q.w, t, sv, &near);
+    if (!c && !near) return false;
+    imp = nee_importance(*q.s, ei, q.p, q.n, q.tri, U);
+    if (!(imp > 0)) return false;
+    if (near && U) TIE(*U, 19);
+    return c;
+}
+
+// Sum of the importances of the billboards crossed by x -> y, edge `skip`
+// left out.
+double nee_crossed_sum(const NeeQuery& q, const V3d& y, int skip, Unit* U) {
+    double sum = 0;
+    for (int ei = 0; ei < (int)q.s->edges.size(); ++ei) {
+        if (ei == skip || q.s->edges[ei].kind == 0) continue;
+        double t, sv, imp;
+        if (nee_cross(q, ei, y, t, sv, imp, U)) sum += imp;
+    }
+    return sum;
+}
+
+// Whether a light point direction is used by the strategy (above x's tangent
+// plane; for one-sided emitters, on the emitting side); with near-tie flags.
+bool nee_usable(const NeeQuery& q, const V3d& dh, int lt, Unit* U) {
+    double cp = dot(q.n, dh);
+    if (U && std::fabs(cp) < kTieSign) TIE(*U, 19);
+    if (!(cp > 0)) return false;
+    if (q.s->two_sided) return true;
+    double cy = -dot(normalize(q.s->face_n(lt)), dh);
+    if (U && std::fabs(cy) < kTieCos) TIE(*U, 19);
+    return cy > 0;
+}
+
+// Density p_N of the billboard strategy at (edge ei, t, sv), in dt ds.
+double nee_pdf(const NeeQuery& q, int ei, double t, double sv, Unit* U) {
+    const Scn& s = *q.s;
+    double imp = nee_importance(s, ei, q.p, q.n, q.tri, U);
+    if (!(imp > 0) || s.atot <= 0) return 0;
+    Billboard B = billboard(s, s.edges[ei], q.p);
+    if (!B.ok) return 0;
+    V3d b = B.pa + B.ah * (B.L * t) + B.v * sv;
+    V3d d = b - q.p;
+    V3d dh = normalize(d);
+    double cb = std::fabs(dot(dh, B.nb));
+    double acc = 0;
+    for (int lt : s.lights) {
+        TriHit h = tri_test(s, lt, q.p, d, 1.0, 1e300);
+        if (!h.valid) continue;
+        if (U && h.t > 1 - kTieLight && std::fabs(h.m) < kTieLight) TIE(*U, 21);
+        if (U && h.m > -kTieLight && std::fabs(h.t - 1) < kTieLight) TIE(*U, 21);
+        if (!h.ok) continue;
+        if (!nee_usable(q, dh, lt, U)) continue;
+        double cy = std::fabs(dot(normalize(s.face_n(lt)), dh));
+        if (!(cy > 0)) continue;
+        V3d y = q.p + d * h.t;
+        double sum = imp + nee_crossed_sum(q, y, ei, U);
+        acc += h.t * h.t * cb / cy * imp / sum;
+    }
+    return acc * B.L / s.atot;
+}
+
+// One draw of the billboard strategy from uniforms ul = (light pick, two
+// point uniforms) and the race uniforms of stream rs (edge e: block 2 + e,
+// first uniform). Returns the edge (or -1) and its strip coordinates.
+int nee_sample(const NeeQuery& q, const double ul[3], const Stream& rs, double& t, double& sv, Unit* U) {
+    const Scn& s = *q.s;
+    if (s.lights.empty()) return -1;
+    Unit dummy;
+    int li = cdf_pick(s.lcdf, ul[0], U ? *U : dummy);
+    int lt = s.lights[li];
+    V3d a = s.p(s.I[3 * lt]), b = s.p(s.I[3 * lt + 1]), c = s.p(s.I[3 * lt + 2]);
+    double su = std::sqrt(ul[1]);
+    V3d y = a * (1 - su) + b * (su * (1 - ul[2])) + c * (su * ul[2]);
+    if (!nee_usable(q, normalize(y - q.p), lt, U)) return -1;
+    int best = -1;
+    double k1 = 1e300, k2 = 1e300;
+    for (int ei = 0; ei < (int)s.edges.size(); ++ei) {
+        if (s.edges[ei].kind == 0) continue;
+        double te, se, imp;
+        if (!nee_cross(q, ei, y, te, se, imp, U)) continue;
+        double u[4];
+        rs.block(2u + (uint32_t)ei, u);
+        double key = -std::log(1.0 - u[0]) / imp;
+        if (key < k1) { k2 = k1; k1 = key; best = ei; t = te; sv = se; }
+        else if (key < k2) k2 = key;
+    }
+    if (U && best >= 0 && k2 < 1e300 && k2 - k1 <= kTieRace * k2) TIE(*U, 20);
+    return best;
+}
+
+// One-sample mixture of the billboard strategy (probability alpha) and the
+// hierarchy. rk: the vertex's secondary-edge stream (root uniform and t in
+// block 0, level uniforms from block 1); rn: its billboard stream (block 0:
+// strategy choice and light uniforms, block 1: s of hierarchy draws, race
+// uniforms from block 2). Returns the edge (or -1), its parameter t and the
+// mixture density in (e, t).
+int nee_mix_draw(const TreeQuery& tq, double w, double alpha, const Stream& rk, const Stream& rn, double& t, double& pdf,
+                 Unit* U) {
+    NeeQuery q{tq.s, tq.p, tq.n, tq.tri, w};
+    double c0[4], c1[4];
+    rn.block(0, c0);
+    rn.block(1, c1);
+    if (U && std::fabs(c0[0] - alpha) < kTieU) TIE(*U, 22);
+    int ei;
+    double sv, ph;
+    if (c0[0] < alpha) {
+        ei = nee_sample(q, c0 + 1, rn, t, sv, U);
+        if (ei < 0) return -1;
+        ph = tree_pdf_edge(tq, ei, U);
+    } else {
+        double b0[4], cache[4];
+        rk.block(0, b0);
+        int cached = -1;
+        auto level_u = [&](int lev) {
+            int blk = 1 + lev / 4;
+            if (blk != cached) { rk.block((uint32_t)blk, cache); cached = blk; }
+            return cache[lev % 4];
+        };
+        ei = tree_sample(tq, b0[0], level_u, ph, U);
+        if (ei < 0) return -1;
+        t = b0[1];
+        sv = (c1[0] - 0.5) * w;
+    }
+    pdf = alpha * w * nee_pdf(q, ei, t, sv, U) + (1 - alpha) * ph;
+    return pdf > 0 ? ei : -1;
+}
+
+// ---------------------------------------------------------------------------
 // Per-unit evaluation
 // ---------------------------------------------------------------------------
 struct Ctx {
@@ -1371,6 +1633,7 @@ struct Ctx {
     uint32_t k0, k1;
     std::vector<double> qcdf;   // CDF of the proposal distribution over all edges (secondary mixture)
     bool mix_p = false, mix_s = false, harvest = false;
+    double nee_w = 0;           // billboard width of the secondary billboard strategy
 };
 
 struct Acc {
@@ -1474,7 +1737,13 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                     return cache[lev % 4];
                 };
                 int ei;
-                if (C.mix_s) {
+                double te_draw = -1;
+                if (o.enee > 0) {
+                    // the billboard strategy mixed with the hierarchy: the
+                    // draw carries its own edge parameter and mixture density
+                    Stream rn{sid, o.view_id, TAG_ENEE + (uint32_t)k, C.k0, C.k1};
+                    ei = nee_mix_draw(q, C.nee_w, o.enee, rk, rn, te_draw, pdf, &U);
+                } else if (C.mix_s) {
                     // proposal mixture: the component from the block's third
                     // uniform, a proposal draw from its fourth
                     if (std::fabs(b0[2] - o.mix) < kTieU) TIE(U, 15);
@@ -1510,7 +1779,7 @@ void run_unit(const Ctx& C, int m, Acc& acc) {
                 if (!disc_from(s, e, p, &U.flag)) continue;
                 V3d pa = s.p(e.va), pb = s.p(e.vb);
                 // the point on the edge: uniform in t, or by the clamped cosine
-                double te = b0[1], pdf_t = 1.0;
+                double te = te_draw >= 0 ? te_draw : b0[1], pdf_t = 1.0;
                 if (o.edge_t_mode == 1) {
                     if (!cosine_edge_t(p, nsv, pa, pb, b0[1], te, &U.flag)) continue;
                     double Tc = cosine_arc_integral(p, nsv, pa, pb);
@@ -1689,8 +1958,8 @@ double orc_edge_t_cosine_pdf(const double p[3], const double n[3], const double 
     return cosine_edge_pdf(P, N, A, B, t, cosine_arc_integral(P, N, A, B));
 }
 
-void orc_tie_reasons(int64_t out[20], int32_t reset) {
-    for (int i = 0; i < 20; ++i) {
+void orc_tie_reasons(int64_t out[24], int32_t reset) {
+    for (int i = 0; i < 24; ++i) {
         out[i] = g_reason[i];
         if (reset) g_reason[i] = 0;
     }
@@ -1804,6 +2073,64 @@ int orc_edge_tree_select(const orc_scene* sd, const orc_camera* c, const double 
     return ORC_OK;
 }
 
+double orc_edge_nee_width(const orc_scene* sd) {
+    Scn s;
+    if (prepare(sd, s)) return -1;
+    return nee_width_default(s);
+}
+
+int orc_edge_nee_sample(const orc_scene* sd, const double p[3], const double n[3], int32_t tri, double width,
+                        int32_t count, uint64_t seed, int32_t* edge, double* t, double* sv, uint8_t* flags) {
+    Scn s;
+    int rc = prepare(sd, s);
+    if (rc) return rc;
+    if (!(width > 0) || tri < -1 || tri >= s.T) return ORC_EINVAL;
+    NeeQuery q{&s, V3d{p[0], p[1], p[2]}, V3d{n[0], n[1], n[2]}, tri, width};
+    for (int i = 0; i < count; ++i) {
+        Stream rn{(uint32_t)i, 0, TAG_ENEE, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+        double c0[4];
+        rn.block(0, c0);
+        Unit U;
+        t[i] = sv[i] = 0;
+        edge[i] = nee_sample(q, c0 + 1, rn, t[i], sv[i], &U);
+        if (flags) flags[i] = U.flag;
+    }
+    return ORC_OK;
+}
+
+int orc_edge_nee_pdf(const orc_scene* sd, const double p[3], const double n[3], int32_t tri, double width,
+                     int32_t count, const int32_t* edge, const double* t, const double* sv, double* pdf) {
+    Scn s;
+    int rc = prepare(sd, s);
+    if (rc) return rc;
+    if (!(width > 0) || tri < -1 || tri >= s.T) return ORC_EINVAL;
+    NeeQuery q{&s, V3d{p[0], p[1], p[2]}, V3d{n[0], n[1], n[2]}, tri, width};
+    for (int i = 0; i < count; ++i) {
+        if (edge[i] < 0 || edge[i] >= (int)s.edges.size()) return ORC_EINVAL;
+        pdf[i] = nee_pdf(q, edge[i], t[i], sv[i], nullptr);
+    }
+    return ORC_OK;
+}
+
+int orc_edge_nee_mix_sample(const orc_scene* sd, const orc_camera* c, const double p[3], const double n[3],
+                            int32_t tri, double width, double alpha, int32_t count, uint64_t seed, int32_t* edge,
+                            double* t, double* pdf) {
+    Scn s;
+    ETree et;
+    int rc = tree_setup(sd, c, s, et);
+    if (rc) return rc;
+    if (!(width > 0) || !(alpha >= 0 && alpha < 1) || tri < -1 || tri >= s.T) return ORC_EINVAL;
+    TreeQuery q{&s, &et, V3d{p[0], p[1], p[2]}, V3d{n[0], n[1], n[2]}, tri};
+    uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    for (int i = 0; i < count; ++i) {
+        Stream rk{(uint32_t)i, 0, TAG_SEDGE + 1, k0, k1};
+        Stream rn{(uint32_t)i, 0, TAG_ENEE + 1, k0, k1};
+        t[i] = pdf[i] = 0;
+        edge[i] = nee_mix_draw(q, width, alpha, rk, rn, t[i], pdf[i], nullptr);
+    }
+    return ORC_OK;
+}
+
 void orc_secondary_forms(const double p_[3], const double v0_[3], const double v1_[3], double t, const double m0_[3],
                          const double nm_[3], double area_form[9], double dir_form[9]) {
     V3d p{p_[0], p_[1], p_[2]}, v0{v0_[0], v0_[1], v0_[2]}, v1{v1_[0], v1_[1], v1_[2]};
@@ -1862,6 +2189,11 @@ int orc_render(const orc_scene* sd, const orc_camera* oc, const orc_options* o, 
     // (the kept edge has no closed-form probability to mix with)
     if (o->edge_candidates < 0 || o->edge_candidates > 64) return ORC_EINVAL;
     if (o->edge_candidates > 1 && mix && (o->mix_terms & 2)) return ORC_EINVAL;
+    // billboard strategy: alpha in [0, 1), uniform edge points, one descent
+    if (!(o->enee >= 0 && o->enee < 1) || !(o->enee_width >= 0)) return ORC_EINVAL;
+    if (o->enee > 0 && (o->edge_t_mode != 0 || o->edge_candidates > 1 || (mix && (o->mix_terms & 2))))
+        return ORC_EINVAL;
+    C.nee_w = o->enee_width > 0 ? o->enee_width : nee_width_default(s);
     C.mix_p = mix && (o->mix_terms & 1);
     C.mix_s = mix && (o->mix_terms & 2) && need_tree;
     if (C.mix_p) build_view_mix(vw, o->edge_pdf, o->mix, vw);

@@ -86,6 +86,15 @@ typedef struct {
      * by weighted reservoir sampling (weight W / (M imp) in place of 1/pdf).
      * Not with a secondary proposal mixture. */
     int32_t edge_candidates;
+    /* Next event estimation for edges: with probability enee (in [0, 1); 0 =
+     * off) the secondary edge sample comes from the billboard strategy (a
+     * light point, the billboards the segment to it crosses, one chosen by
+     * importance), otherwise from the hierarchy; every sample is weighted by
+     * the mixture density. enee_width: billboard width (0 = 2% of the mean
+     * absolute deviation of the vertex positions, L2 over the coordinates).
+     * Uniform edge points, one descent, no secondary proposal mixture. */
+    double  enee;
+    double  enee_width;
 } orc_options;
 
 typedef struct {
@@ -115,7 +124,7 @@ int  orc_render(const orc_scene* s, const orc_camera* c, const orc_options* o, o
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
 /* Diagnostic counters of near-tie flags by reason (see oracle.cpp). */
-void orc_tie_reasons(int64_t out[20], int32_t reset);
+void orc_tie_reasons(int64_t out[24], int32_t reset);
 
 /* Unique undirected edges: rows (va, vb, f0, f1), va < vb, f1 = -1 on a boundary. */
 int  orc_edges(const orc_scene* s, int32_t* num_edges, int32_t* rows /* [E][4] or NULL */);
@@ -153,6 +162,25 @@ int  orc_edge_tree_sample(const orc_scene* s, const orc_camera* c, const double 
 int    orc_edge_t_cosine(const double p[3], const double n[3], const double v0[3], const double v1[3], int32_t count,
                          const double* u, double* t, double* pdf_t);
 double orc_edge_t_cosine_pdf(const double p[3], const double n[3], const double v0[3], const double v1[3], double t);
+
+/* Next event estimation for edges at shading point p (normal n, on triangle
+ * tri or -1), billboards of full width `width`:
+ *  - the default width of the scene;
+ *  - count draws of the billboard strategy alone, draw i from Philox stream
+ *    (i, 0, 32; seed): edge (-1: none), strip coordinates (t, s), and 1 in
+ *    flags[i] (may be NULL) when a decision was within rounding of a tie;
+ *  - its density in dt ds at given (edge, t, s);
+ *  - count draws of the mixture with the hierarchy of camera c (probability
+ *    alpha for the billboards; streams (i, 0, 2) and (i, 0, 33); seed): edge
+ *    (-1: none), t and the mixture density in (e, t). */
+double orc_edge_nee_width(const orc_scene* s);
+int    orc_edge_nee_sample(const orc_scene* s, const double p[3], const double n[3], int32_t tri, double width,
+                           int32_t count, uint64_t seed, int32_t* edge, double* t, double* sv, uint8_t* flags);
+int    orc_edge_nee_pdf(const orc_scene* s, const double p[3], const double n[3], int32_t tri, double width,
+                        int32_t count, const int32_t* edge, const double* t, const double* sv, double* pdf);
+int    orc_edge_nee_mix_sample(const orc_scene* s, const orc_camera* c, const double p[3], const double n[3],
+                               int32_t tri, double width, double alpha, int32_t count, uint64_t seed,
+                               int32_t* edge, double* t, double* pdf);
 
 /* Secondary boundary factor in both measures for one edge point (for the
  * identity test between the thesis's area form and the direction form).

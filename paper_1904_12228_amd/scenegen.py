@@ -253,15 +253,16 @@ def config1(seed=0):
 # configuration 2: random soup, ground, one quad light, direct lighting
 # --------------------------------------------------------------------------
 
-def soup(seed=0, n_tris=1000, width=256, height=256, spp=16, light_emission=10.0):
+def soup(seed=0, n_tris=1000, width=256, height=256, spp=16, light_emission=10.0, light_size=0.5):
     """Random non-intersecting triangle soup in the unit cube on a ground quad
-    under one 0.5x0.5 quad light (Lambertian, albedo U[0.2,0.8])."""
+    under one light_size x light_size quad light (Lambertian, albedo
+    U[0.2,0.8])."""
     rng = _rng(seed)
     ground_y = -0.05
     gv, gf = _quad((-1.5, ground_y, -1.5), (-1.5, ground_y, 2.5),
                    (2.5, ground_y, 2.5), (2.5, ground_y, -1.5))
     # light at y=1.8 above the cube centre, facing -y
-    h = 0.25
+    h = 0.5 * light_size
     lv, lf = _quad((0.5 - h, 1.8, 0.5 - h), (0.5 + h, 1.8, 0.5 - h),
                    (0.5 + h, 1.8, 0.5 + h), (0.5 - h, 1.8, 0.5 + h))
     tris = []
