@@ -144,6 +144,27 @@ typedef struct {
      * proposal mixture and no geometry buffer, and is not taken by batches;
      * otherwise, or M > 16: DR_ERROR_INVALID_VALUE. */
     int32_t  edge_candidates;
+    /* Next event estimation for edges (drRenderBackward only; Ch. 5, Next
+     * event estimation for edges). edge_nee = alpha in [0, 1) (0: off): each
+     * secondary edge sample comes with probability alpha from the strip
+     * strategy and otherwise from the edge hierarchy. The strip strategy
+     * draws a light point y as next-event estimation does, widens every edge
+     * into a strip of width edge_nee_width that faces the shading point x,
+     * and picks one of the strips the segment x -> y crosses in proportion to
+     * its edge's importance; the crossing, projected onto the edge, is the
+     * edge point. Every sample is weighted by the density of the mixture
+     * (one-sample multiple importance sampling), so the estimate stays
+     * unbiased for any alpha and width. Emitter edges and edges that are no
+     * discontinuity from x are left to the hierarchy. edge_nee_width = 0:
+     * the scene's default, the L2 norm over the coordinates of 2% of the
+     * mean absolute deviation of the vertex positions (computed at
+     * drSceneCreate / drSceneUpdateVertices; drSceneRefit keeps it).
+     * alpha > 0 needs max_depth <= 3, edge_t_mode 0, edge_candidates <= 1,
+     * no secondary proposal mixture, no edge_stats and no geometry buffer,
+     * and is not taken by batches; otherwise, alpha outside [0, 1) or a
+     * negative or non-finite width: DR_ERROR_INVALID_VALUE. */
+    float    edge_nee;
+    float    edge_nee_width;
 } drRenderOptions;
 
 /* Creates a scene: validates sizes and indices (host copy of the topology),

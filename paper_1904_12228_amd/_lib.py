@@ -47,7 +47,7 @@ class RenderOptions(C.Structure):
                 ("view_id", C.c_uint32), ("terms", C.c_uint32), ("unit_mask", C.c_void_p),
                 ("edge_pdf", C.c_void_p), ("edge_mix", C.c_float), ("edge_mix_terms", C.c_uint32),
                 ("edge_stats", C.c_void_p), ("aov", C.c_int32), ("edge_t_mode", C.c_int32),
-                ("edge_candidates", C.c_int32)]
+                ("edge_candidates", C.c_int32), ("edge_nee", C.c_float), ("edge_nee_width", C.c_float)]
 
 
 class Profile(C.Structure):

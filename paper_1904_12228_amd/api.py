@@ -40,10 +40,11 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 def options_struct(spp, max_depth, seed=0, view_id=0, terms=0, unit_mask=None, edge_pdf=None, edge_mix=0.0,
-                   edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0, edge_candidates=0) -> _lib.RenderOptions:
+                   edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0, edge_candidates=0, edge_nee=0.0,
+                   edge_nee_width=0.0) -> _lib.RenderOptions:
     return _lib.RenderOptions(int(spp), int(max_depth), int(seed), int(view_id), int(terms), _ptr(unit_mask),
                               _ptr(edge_pdf), float(edge_mix), int(edge_mix_terms), _ptr(edge_stats), int(aov),
-                              int(edge_t), int(edge_candidates))
+                              int(edge_t), int(edge_candidates), float(edge_nee), float(edge_nee_width))
 
 
 # geometry-buffer channels of drRenderOptions.aov
@@ -108,13 +109,20 @@ class Scene:
 
     def render_backward(self, cam, spp, max_depth, d_image, seed=0, view_id=0, terms=0, unit_mask=None,
                         want=("vertices", "albedo", "camera"), outs=None, edge_pdf=None, edge_mix=0.0,
-                        edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0, edge_candidates=0):
+                        edge_mix_terms=0, edge_stats=None, aov=0, edge_t=0, edge_candidates=0, edge_nee=0.0,
+                        edge_nee_width=0.0):
         """Gradients w.r.t. vertices [V,3], albedo [T] and camera [9]. With
         edge_pdf ([E] device distribution) and edge_mix > 0 the edge samples
         are drawn from the proposal mixture; edge_stats ([E] float32 device
         tensor) receives the harvest statistic. aov selects the image being
         differentiated, as in render. edge_t = 1 draws the point on each
-        secondary edge by the clamped cosine instead of uniformly."""
+        secondary edge by the clamped cosine instead of uniformly.
+        edge_candidates = M > 1 selects each secondary edge by M samples down
+        the hierarchy and reservoir selection. edge_nee = alpha in (0, 1)
+        draws each secondary edge sample with probability alpha from the
+        edge strips crossed by a segment to a light point (next event
+        estimation for edges), edge_nee_width their width (0: the scene's
+        default)."""
         d_image = _dev(d_image, torch.float32, self.device)
         x0, y0, x1, y1 = cam.win()
         assert d_image.numel() == (7 if aov == 8 else 1) * (y1 - y0) * (x1 - x0), "d_image size"
@@ -130,7 +138,7 @@ class Scene:
         if edge_stats is not None:
             assert edge_stats.dtype == torch.float32 and edge_stats.is_contiguous() and edge_stats.numel() == self.num_edges
         o = options_struct(spp, max_depth, seed, view_id, terms, unit_mask, edge_pdf, edge_mix, edge_mix_terms,
-                           edge_stats, aov, edge_t, edge_candidates)
+                           edge_stats, aov, edge_t, edge_candidates, edge_nee, edge_nee_width)
         _lib.check(_lib.load().drRenderBackward(self._h, C.byref(c), C.byref(o), _ptr(d_image), _ptr(dv), _ptr(da),
                                                 _ptr(dc), _stream()), "drRenderBackward")
         return dv, da, dc

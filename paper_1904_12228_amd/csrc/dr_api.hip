@@ -79,6 +79,11 @@ bool valid_options(const drRenderOptions* o) {
            (o->edge_candidates <= 1 ||
             (o->max_depth <= 3 && o->aov == 0 &&
              !(o->edge_pdf && o->edge_mix > 0.0f &&
+               (o->edge_mix_terms == 0 || (o->edge_mix_terms & DR_TERM_SECONDARY))))) &&
+           o->edge_nee >= 0.0f && o->edge_nee < 1.0f && o->edge_nee_width >= 0.0f && std::isfinite(o->edge_nee_width) &&
+           (o->edge_nee == 0.0f ||
+            (o->max_depth <= 3 && o->aov == 0 && o->edge_t_mode == 0 && o->edge_candidates <= 1 && !o->edge_stats &&
+             !(o->edge_pdf && o->edge_mix > 0.0f &&
                (o->edge_mix_terms == 0 || (o->edge_mix_terms & DR_TERM_SECONDARY)))));
 }
 

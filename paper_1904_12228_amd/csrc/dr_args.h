@@ -26,6 +26,7 @@ struct RenderArgs {
     int aov;           // 0: radiance; 1..7: geometry-buffer channel (the _aov kernels)
     int edge_t;        // point on a secondary edge: 0 uniform in t, 1 by the clamped cosine
     int cands;         // secondary edge selection: <= 1 one descent, M > 1 M-sample descent + reservoir
+    float nee, nee_w;  // next event estimation for edges: probability of the strip strategy (0: off), strip width
 };
 
 // Learned-proposal mixture and harvest (the <.., MIX = true> kernel variants).

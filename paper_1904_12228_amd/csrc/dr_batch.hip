@@ -102,7 +102,7 @@ extern "C" drStatus drBatchCreate(drBatch* out, drScene s, int32_t n, const drCa
         const drRenderOptions& o = opts[v];
         if (!valid_camera(&cams[v]) || !valid_options(&o) || !images[v] || !d_images[v]) return DR_ERROR_INVALID_VALUE;
         if (o.max_depth != opts[0].max_depth || o.edge_pdf || o.edge_stats || o.edge_mix != 0.0f || o.aov != 0 ||
-            o.edge_candidates > 1)
+            o.edge_candidates > 1 || o.edge_nee > 0.0f)
             return DR_ERROR_INVALID_VALUE;
     }
     drBatch_t* b = new drBatch_t();

@@ -382,6 +382,22 @@ static void sah_topology(const float* P, const int* I, int T, int lim, std::vect
     }
 }
 
+// Default strip width of next event estimation for edges (Ch. 5, Next event
+// estimation for edges): the L2 norm over the three coordinates of 2% of the
+// mean absolute deviation of the vertex positions.
+static float strip_width(const float* P, int V) {
+    double w2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double mean = 0.0, dev = 0.0;
+        for (int v = 0; v < V; ++v) mean += P[3 * (size_t)v + k];
+        mean /= V;
+        for (int v = 0; v < V; ++v) dev += std::fabs(P[3 * (size_t)v + k] - mean);
+        double m = 0.02 * dev / V;
+        w2 += m * m;
+    }
+    return (float)std::sqrt(w2);
+}
+
 drStatus build_scene_static(drScene_t* s, hipStream_t st) {
     const int BS = 256;
     int T = s->T, V = s->V;
@@ -393,13 +409,15 @@ drStatus build_scene_static(drScene_t* s, hipStream_t st) {
                                       s->scal.as<float>());
     k_tri_prep<<<blocks(T, BS), BS, 0, st>>>(s->P.as<float>(), s->I.as<int>(), T, s->tri.as<float4>());
     k_bounds<<<1, 256, 0, st>>>(s->P.as<float>(), V, s->I.as<int>(), T, s->scal.as<float>());
+    // host copy of the vertices: the SAH topology and the default strip width
+    s->hP.resize(3 * (size_t)V);
+    DR_CHECK(hipMemcpyAsync(s->hP.data(), s->P.p, sizeof(float) * 3 * V, hipMemcpyDeviceToHost, st));
+    DR_CHECK(hipStreamSynchronize(st));
+    for (float x : s->hP)
+        if (!std::isfinite(x)) return DR_ERROR_INVALID_VALUE;   // no meaningful bounds or splits
+    s->nee_w = strip_width(s->hP.data(), V);
     if (T > 1 && s->sah_bvh) {
         // topology on the host from the current vertices; links and boxes on the device
-        s->hP.resize(3 * (size_t)V);
-        DR_CHECK(hipMemcpyAsync(s->hP.data(), s->P.p, sizeof(float) * 3 * V, hipMemcpyDeviceToHost, st));
-        DR_CHECK(hipStreamSynchronize(st));
-        for (float x : s->hP)
-            if (!std::isfinite(x)) return DR_ERROR_INVALID_VALUE;   // no meaningful bounds or splits
         int lg = 0;
         while ((1 << lg) < T) ++lg;
         sah_topology(s->hP.data(), s->hI.data(), T, std::max(56 - lg, 0), s->hchild, s->hparent, s->horder);

@@ -31,6 +31,9 @@ constexpr int kSideBlockBase = 32;    // Philox block base of secondary side pat
 constexpr uint32_t kTagCam = 0, kTagPedge = 1, kTagSedge = 1;  // SEDGE_k = 1 + k
 constexpr uint32_t kTagSelect = 16;     // SELECT_k = 16 + k: uniforms of the multi-sample edge selection
 constexpr int kSelectMax = 16;          // largest number of samples of the multi-sample edge selection
+constexpr uint32_t kTagEnee = 32;       // ENEE_k = 32 + k: uniforms of next event estimation for edges
+constexpr float kStripPad = 0.5005f;    // hierarchy boxes grown by this x strip width when walking a segment
+constexpr float kWalkPad = 1e-5f;       // ... plus this x scene diagonal (FP32 rounding of the boxes)
 
 // ---------------------------------------------------------------------------
 // vector math

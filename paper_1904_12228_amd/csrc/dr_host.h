@@ -54,6 +54,7 @@ struct drScene_t {
     int two_sided = 0;
     float background = 0.0f;
     float diag = 0.0f, tmin = 0.0f, atot = 0.0f;
+    float nee_w = 0.0f;              // default strip width of next event estimation for edges
     int bvh_depth = 0;               // internal nodes on the longest root-to-leaf path
     int grad_shards = 256;           // copies of the gradient arrays (power of two; set by drSceneCreate)
     uint64_t version = 0;            // bumps on every vertex update

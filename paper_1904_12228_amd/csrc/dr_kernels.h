@@ -941,6 +941,242 @@ __device__ inline float cosine_edge_pdf(v3 p, v3 n, v3 pa, v3 pb, float t, float
 }
 
 // ---------------------------------------------------------------------------
+// Next event estimation for edges (Ch. 5, Next event estimation for edges):
+// a second strategy for the secondary edge sample. A light point y is drawn
+// as next-event estimation draws it; every edge is widened into a strip of
+// width w that faces the shading point x, { pa + t (pb - pa) + s v :
+// t in [0, 1], |s| <= w/2 }, v the unit vector orthogonal to the edge and to
+// pa - x; among the strips the segment x -> y crosses, one is chosen in
+// proportion to the edge's importance (an exponential race: edge e's key
+// -log(1 - u_e) / imp_e with u_e from its own Philox block, the smallest key
+// wins, so the choice does not depend on the order of the hierarchy walk
+// that finds the crossings), and the crossing's parameter t is the point on
+// the edge. Its density in (t, s): the ray from x through the strip point b
+// meets the lights at y = x + mu (b - x), mu > 1, each drawn with area
+// density 1 / A_lights; with the Jacobian from light area to strip area and
+// the choice among the strips crossed by x -> y,
+//   p_N = |pb - pa| / A_lights * sum_y mu^2 |cos_b| / |cos_y| * imp_e / sum_crossed imp.
+// The strategy is mixed with the hierarchy by one-sample multiple importance
+// sampling (probability alpha for the strips, a uniform s across the strip
+// for hierarchy draws): the sample's density in (e, t) is
+// alpha w p_N + (1 - alpha) p_H. Importance: that of a hierarchy leaf
+// without the parent-box rule, zero for the shading triangle's own edges,
+// emitter edges and edges that are no discontinuity as seen from x. Light
+// points behind x's tangent plane or on a one-sided emitter's back are not
+// used.
+// ---------------------------------------------------------------------------
+struct Strip {
+    v3 pa, ah, v, nb;    // edge start, unit edge direction, unit width direction, unit normal
+    float L;             // edge length
+    bool ok;
+};
+
+__device__ inline Strip strip_of(const SceneView& s, int4 e, v3 x) {
+    Strip B;
+    B.pa = ld3(s.P, e.x);
+    v3 a = ld3(s.P, e.y) - B.pa;
+    B.L = len(a);
+    B.ok = false;
+    if (!(B.L > 0.0f)) return B;
+    B.ah = a * (1.0f / B.L);
+    v3 c = cross(B.ah, B.pa - x);
+    float cl = len(c);
+    if (!(cl > 0.0f)) return B;
+    B.v = c * (1.0f / cl);
+    B.nb = cross(B.ah, B.v);
+    B.ok = true;
+    return B;
+}
+
+// Crossing of the segment x -> x + d (both ends excluded) with the strip.
+__device__ inline bool strip_cross(const Strip& B, v3 x, v3 d, float w, float& t, float& sv) {
+    if (!B.ok) return false;
+    float den = dot(d, B.nb);
+    if (den == 0.0f) return false;
+    float lam = dot(B.pa - x, B.nb) / den;
+    v3 r = x + d * lam - B.pa;
+    t = dot(r, B.ah) / B.L;
+    sv = dot(r, B.v);
+    return t >= 0.0f && t <= 1.0f && fabsf(sv) <= 0.5f * w && lam > 0.0f && lam < 1.0f;
+}
+
+__device__ inline float strip_importance(const SceneView& s, int ei, const TreeCtx& q) {
+    if (s.ekind[ei] == 0) return 0.0f;
+    int4 e = s.edges[ei];
+    if (e.z == q.tri || e.w == q.tri) return 0.0f;
+    if (s.emi[e.z] > 0.0f || (e.w >= 0 && s.emi[e.w] > 0.0f)) return 0.0f;
+    if (s.ekind[ei] == 2 && !silhouette_from(s, e, q.p)) return 0.0f;
+    v3 a = ld3(s.P, e.x), b = ld3(s.P, e.y);
+    float lo[3] = {fminf(a.x, b.x), fminf(a.y, b.y), fminf(a.z, b.z)};
+    float hi[3] = {fmaxf(a.x, b.x), fmaxf(a.y, b.y), fmaxf(a.z, b.z)};
+    float cb = cos_bound(lo, hi, q.p, q.n, q.t1, q.t2, q.hz);
+    if (cb <= 0.0f) return 0.0f;
+    v3 dc = (a + b) * 0.5f - q.p;
+    return len(b - a) * cb * rsqrtf(dot(dc, dc));
+}
+
+// Segment x -> x + d (parameter in [0, 1]) against a box grown by pad. A zero
+// direction component on the box's boundary gives NaN bounds, which fminf /
+// fmaxf ignore: the test then errs towards a visit.
+__device__ inline bool seg_box(const float* lo, const float* hi, float pad, v3 x, v3 inv) {
+    float t0 = 0.0f, t1 = 1.0f;
+    const float xv[3] = {x.x, x.y, x.z}, iv[3] = {inv.x, inv.y, inv.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float a = (lo[k] - pad - xv[k]) * iv[k], b = (hi[k] + pad - xv[k]) * iv[k];
+        t0 = fmaxf(t0, fminf(a, b));
+        t1 = fminf(t1, fmaxf(a, b));
+    }
+    return t0 <= t1;
+}
+
+// Visits every edge whose hierarchy box, grown by pad, meets the segment
+// x -> x + d: depth first, child 0 first, without a stack (the parent links
+// lead back up; every node is entered once and left twice).
+template <class F, class W>
+__device__ inline void strip_walk(const SceneView& s, const TreeView& tv, v3 x, v3 d, float pad, W& wk, F&& visit) {
+    v3 inv = {1.0f / d.x, 1.0f / d.y, 1.0f / d.z};
+    int node = 0, c = 0;
+    for (long guard = 6L * s.E + 8; guard > 0; --guard) {
+        if (c < 2) {
+            const ETNode* N = tv.nodes + node;
+            int ref = N->child[c];
+            if (ref != 0) {
+                wk.tree();
+                if (seg_box(N->ch[c].lo, N->ch[c].hi, pad, x, inv)) {
+                    if (ref > 0) {
+                        node = ref;
+                        c = 0;
+                        continue;
+                    }
+                    visit(~ref);
+                }
+            }
+            ++c;
+        } else {
+            if (node == 0) return;
+            int pc = tv.enpar[node];
+            node = pc >> 1;
+            c = (pc & 1) + 1;
+        }
+    }
+    atomicOr(s.err, kErrTreeDepth);
+}
+
+// Sum of the importances of the strips crossed by x -> y, edge `skip` left out.
+template <class W>
+__device__ inline float strip_crossed_sum(const SceneView& s, const TreeView& tv, const TreeCtx& q, float w, v3 y,
+                                          int skip, W& wk) {
+    float sum = 0.0f;
+    v3 d = y - q.p;
+    strip_walk(s, tv, q.p, d, kStripPad * w + kWalkPad * s.diag, wk, [&](int ei) {
+        if (ei == skip) return;
+        float t, sv;
+        if (!strip_cross(strip_of(s, s.edges[ei], q.p), q.p, d, w, t, sv)) return;
+        sum += strip_importance(s, ei, q);
+    });
+    return sum;
+}
+
+// Whether the direction dh towards a point of light triangle g is used: above
+// the tangent plane and, for one-sided emitters, on the emitting side.
+__device__ inline bool strip_light_usable(const SceneView& s, const TreeCtx& q, v3 dh, const TriGeom& g) {
+    if (!(dot(q.n, dh) > 0.0f)) return false;
+    if (s.two_sided) return true;
+    return -dot(nrm(cross(g.e1, g.e2)), dh) > 0.0f;
+}
+
+// Density of the strip strategy at (edge ei, t, sv), in dt ds.
+template <class W>
+__device__ inline float strip_pdf(const SceneView& s, const TreeView& tv, const TreeCtx& q, float w, int ei, float t,
+                                  float sv, W& wk) {
+    float imp = strip_importance(s, ei, q);
+    if (!(imp > 0.0f) || s.L == 0) return 0.0f;
+    Strip B = strip_of(s, s.edges[ei], q.p);
+    if (!B.ok) return 0.0f;
+    v3 b = B.pa + B.ah * (B.L * t) + B.v * sv;
+    v3 d = b - q.p;
+    v3 dh = nrm(d);
+    float cb = fabsf(dot(dh, B.nb));
+    float acc = 0.0f;
+    for (int i = 0; i < s.L; ++i) {
+        TriGeom g = tri_geom(s, s.lights[i]);
+        // Moller-Trumbore on the ray x + mu d, both faces, mu > 1
+        v3 pv = cross(d, g.e2);
+        float det = dot(g.e1, pv);
+        if (det == 0.0f) continue;
+        float inv = 1.0f / det;
+        v3 tq = q.p - g.p0;
+        float u = dot(tq, pv) * inv;
+        v3 qv = cross(tq, g.e1);
+        float vv = dot(d, qv) * inv;
+        float mu = dot(g.e2, qv) * inv;
+        if (!(u >= 0.0f && vv >= 0.0f && u + vv <= 1.0f && mu > 1.0f)) continue;
+        if (!strip_light_usable(s, q, dh, g)) continue;
+        float cy = fabsf(dot(nrm(cross(g.e1, g.e2)), dh));
+        if (!(cy > 0.0f)) continue;
+        float sum = imp + strip_crossed_sum(s, tv, q, w, q.p + d * mu, ei, wk);
+        acc += mu * mu * cb / cy * imp / sum;
+    }
+    return acc * B.L / s.atot[0];
+}
+
+// One draw of the strip strategy: light point from c0.y (light), c0.z, c0.w
+// (point), the race's uniforms from rn's blocks 2 + edge id. Returns the
+// edge (or -1) and the crossing's strip coordinates.
+template <class W>
+__device__ inline int strip_sample(const SceneView& s, const TreeView& tv, const TreeCtx& q, float w, float4 c0,
+                                   const Rng& rn, float& t, float& sv, W& wk) {
+    if (s.L == 0) return -1;
+    int lt = s.lights[pick_cdf(s.lcdf, s.L, c0.y)];
+    TriGeom g = tri_geom(s, lt);
+    float su = sqrtf(c0.z);
+    v3 y = g.p0 + g.e1 * (su * (1.0f - c0.w)) + g.e2 * (su * c0.w);
+    v3 d = y - q.p;
+    if (!strip_light_usable(s, q, nrm(d), g)) return -1;
+    int best = -1;
+    float kbest = 3e38f;
+    strip_walk(s, tv, q.p, d, kStripPad * w + kWalkPad * s.diag, wk, [&](int ei) {
+        float te, se;
+        if (!strip_cross(strip_of(s, s.edges[ei], q.p), q.p, d, w, te, se)) return;
+        float imp = strip_importance(s, ei, q);
+        if (!(imp > 0.0f)) return;
+        float key = -logf(1.0f - rn.block(2u + (uint32_t)ei).x) / imp;
+        if (key < kbest) {
+            kbest = key;
+            best = ei;
+            t = te;
+            sv = se;
+        }
+    });
+    return best;
+}
+
+// The mixture draw: with probability a.nee the strips, else the hierarchy
+// (root uniform b0.x, t = b0.y, s from rn's block 1). Returns the edge (or
+// -1), its parameter t and the density in (e, t).
+template <class W>
+__device__ inline int strip_mix_draw(const SceneView& s, const TreeView& tv, const TreeCtx& q, const RenderArgs& a,
+                                     const Rng& rk, float4 b0, const Rng& rn, float& t, float& pdf, W& wk) {
+    float4 c0 = rn.block(0);
+    float w = a.nee_w;
+    int ei;
+    float sv, ph;
+    if (c0.x < a.nee) {
+        ei = strip_sample(s, tv, q, w, c0, rn, t, sv, wk);
+        if (ei < 0) return -1;
+        ph = tree_pdf_edge(tv, q, ei, wk);
+    } else {
+        ei = tree_sample(tv, q, rk, b0.x, ph, wk);
+        if (ei < 0) return -1;
+        t = b0.y;
+        sv = (rn.block(1).x - 0.5f) * w;
+    }
+    pdf = a.nee * w * strip_pdf(s, tv, q, w, ei, t, sv, wk) + (1.0f - a.nee) * ph;
+    return pdf > 0.0f ? ei : -1;
+}
+
+// ---------------------------------------------------------------------------
 // backward over paths: secondary edges at every vertex + interior adjoint
 // ---------------------------------------------------------------------------
 // PH: 0 = all in one pass; 1 = rebuild the path, sample the secondary edges and
@@ -1315,11 +1551,12 @@ __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArg
 // Each lane rebuilds its unit's path up to its vertex with the adjoint pass's
 // arithmetic (same operations in the same order) and appends its side-path
 // query to segment kk of the queue.
-template <int STK, bool MIX, bool SEL = false>
+template <int STK, bool MIX, bool SEL = false, bool NEE = false>
 __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
                                                      int nvert, MixArgs mx) {
     // no rays are traced here: no traversal stack (STK only names the variant);
-    // SEL: the multi-sample edge selection and its LDS stack of deferred children
+    // SEL: the multi-sample edge selection and its LDS stack of deferred children;
+    // NEE: the strip strategy (next event estimation for edges) mixed with the hierarchy
     __shared__ int sel_stk[SEL ? kSelectMax * 4 * BS : 1];
     int lane = threadIdx.x;
     NoWork wk;
@@ -1373,8 +1610,12 @@ __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderA
             float pdf;
             TreeCtx q = tree_ctx(&s, p, n, tv.cam, t, kHorizon * s.diag, kInsidePad * s.diag);
             int ei;
+            float te_draw = 0.0f;
             do {
-                if (MIX && mx.sec) {
+                if (NEE) {
+                    Rng rn{sid, a.view, kTagEnee + (uint32_t)(kk + 1), a.k0, a.k1};
+                    ei = strip_mix_draw(s, tv, q, a, rk, b0, rn, te_draw, pdf, wk);
+                } else if (MIX && mx.sec) {
                     // proposal mixture: component from the third uniform of the
                     // block, proposal draw from the fourth
                     float pt;
@@ -1398,8 +1639,8 @@ __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderA
                 if (e.z == t || e.w == t) break;
                 if (s.ekind[ei] == 2 && !silhouette_from(s, e, p)) break;
                 v3 pa = ld3(s.P, e.x), pb = ld3(s.P, e.y);
-                float te = b0.y, pdf_t = 1.0f;
-                if (a.edge_t == 1) {
+                float te = NEE ? te_draw : b0.y, pdf_t = 1.0f;
+                if (!NEE && a.edge_t == 1) {
                     float Tc;
                     if (!cosine_edge_t(p, n, pa, pb, b0.y, te, Tc)) break;
                     pdf_t = cosine_edge_pdf(p, n, pa, pb, te, Tc);
@@ -1715,6 +1956,8 @@ static RenderArgs make_args(drScene_t* s, const Cam& cam, const drRenderOptions&
     a.aov = o.aov;
     a.edge_t = o.edge_t_mode;
     a.cands = o.edge_candidates;
+    a.nee = o.edge_nee;
+    a.nee_w = o.edge_nee_width > 0.0f ? o.edge_nee_width : s->nee_w;
     return a;
 }
 

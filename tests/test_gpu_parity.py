@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0, edge_t=0, cands=0):
+def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0, edge_t=0, cands=0, nee=0.0):
     from paper_1904_12228_amd import api
     x0, y0, x1, y1 = cam.win()
     rng = np.random.default_rng(dimg_seed)
@@ -31,8 +31,10 @@ def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0, e
         kw["edge_t"] = edge_t
     if cands:
         kw["edge_candidates"] = cands
+    if nee:
+        kw["enee"] = nee
     print(f"case: V={scene.num_vertices} T={scene.num_triangles} win={cam.win()} spp={spp} depth={depth} seed={seed}"
-          f" aov={aov} edge_t={edge_t} cands={cands}", flush=True)
+          f" aov={aov} edge_t={edge_t} cands={cands} nee={nee}", flush=True)
     orc = oracle_reference(scene, cam, spp, depth, seed, dimg, threads=threads, **kw)
     assert orc["stats"][4] == 0, "camera-level near tie in edge classification"
     mask = torch.as_tensor(orc["mask"], device="cuda")
@@ -40,7 +42,7 @@ def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0, e
     img = S.render(cam, spp, depth, seed, unit_mask=mask, aov=aov)
     dv, da, dc = S.render_backward(cam, spp, depth, torch.as_tensor(dimg, dtype=torch.float32, device="cuda"),
                                    seed=seed, terms=terms, unit_mask=mask, aov=aov, edge_t=edge_t,
-                                   edge_candidates=cands)
+                                   edge_candidates=cands, edge_nee=nee)
     torch.cuda.synchronize()
     assert not S.device_error()
     res = dict(img=img.cpu().numpy(), dv=dv.cpu().numpy(), da=da.cpu().numpy(), dc=dc.cpu().numpy())
@@ -49,7 +51,7 @@ def _run(scene, cam, spp, depth, seed, dimg_seed=0, terms=0, threads=8, aov=0, e
     M = (x1 - x0) * (y1 - y0) * spp
     assert flagged <= 0.05 * M, f"too many near-tie units: {flagged}/{M}"
     case = (f"T={scene.num_triangles} win={cam.win()} spp={spp} depth={depth} terms={terms or 7} edge_t={edge_t}"
-            f"{f' cands={cands}' if cands else ''} flagged={flagged}/{M}")
+            f"{f' cands={cands}' if cands else ''}{f' nee={nee}' if nee else ''} flagged={flagged}/{M}")
     compare("image", res["img"], orc["image"], case=case)
     compare("d_vertices", res["dv"], orc["d_vertices"], orc["mass_vertices"], case=case)
     compare("d_albedo", res["da"], orc["d_albedo"], orc["mass_albedo"], case=case)
@@ -154,6 +156,59 @@ def test_multi_sample_selection_argument_checks():
         with pytest.raises(RuntimeError):
             S.render_backward(cfg.camera, 1, depth, d, edge_candidates=cands)
     S.render_backward(cfg.camera, 1, 1, d, edge_candidates=16)
+    torch.cuda.synchronize()
+    assert not S.device_error()
+    S.close()
+
+
+@pytest.mark.parametrize("nee,terms", [(0.5, 4), (0.5, 7), (0.9, 4)])
+def test_edge_nee_soup_small_light(nee, terms):
+    """Next event estimation for edges: secondary edge samples drawn with
+    probability nee from the edge strips crossed by segments to a small
+    light, the rest from the hierarchy, weighted by the mixture density."""
+    cfg = sg.soup(seed=3, n_tris=40, width=96, height=80, spp=2, light_size=0.15, light_emission=60.0)
+    cam = cfg.camera.with_window(20, 15, 67, 52)
+    _run(cfg.scene, cam, 2, 1, 5, terms=terms, nee=nee)
+
+
+def test_edge_nee_sphere_box_depth3():
+    cfg = sg.sphere_box(seed=1, level=3, width=64, height=64, spp=2, max_depth=3)
+    cam = cfg.camera.with_window(6, 10, 49, 41)
+    _run(cfg.scene, cam, 2, 3, 2, nee=0.5)
+
+
+def test_edge_nee_config3_window():
+    cfg = sg.config3()
+    cam = cfg.camera.with_window(300, 200, 331, 225)
+    _run(cfg.scene, cam, 2, 3, 0, nee=0.5)
+
+
+def test_edge_nee_without_lights():
+    """No emitter: the strip strategy never finds a light point, and every
+    sample is the hierarchy's, weighted by (1 - alpha) times its pdf."""
+    cfg = sg.soup(seed=3, n_tris=40, width=96, height=80, spp=2)
+    scene = cfg.scene.copy()
+    scene.emission[:] = 0.0
+    scene.background = 1.0
+    cam = cfg.camera.with_window(20, 15, 67, 52)
+    _run(scene, cam, 2, 1, 5, terms=4, nee=0.5)
+
+
+def test_edge_nee_argument_checks():
+    from paper_1904_12228_amd import api
+    cfg = sg.soup(seed=3, n_tris=40, width=32, height=32, spp=1)
+    S = api.Scene(cfg.scene)
+    d = torch.ones(32, 32, device="cuda")
+    bad = [dict(edge_nee=1.0), dict(edge_nee=-0.1), dict(edge_nee=float("nan")), dict(edge_nee=0.5, edge_nee_width=-1.0),
+           dict(edge_nee=0.5, edge_nee_width=float("inf")), dict(edge_nee=0.5, edge_t=1),
+           dict(edge_nee=0.5, edge_candidates=4)]
+    for kw in bad:
+        with pytest.raises(RuntimeError):
+            S.render_backward(cfg.camera, 1, 1, d, **kw)
+    with pytest.raises(RuntimeError):
+        S.render_backward(cfg.camera, 1, 4, d, edge_nee=0.5)
+    S.render_backward(cfg.camera, 1, 1, d, edge_nee=0.5)
+    S.render_backward(cfg.camera, 1, 3, d, edge_nee=0.3, edge_nee_width=0.05)
     torch.cuda.synchronize()
     assert not S.device_error()
     S.close()
