@@ -126,7 +126,7 @@ def _sampler_comparison(variants):
     out = {}
     for name, cfg, depth in (("config2", scenegen.config2(), 1), ("config3_window", scenegen.config3(), 3)):
         S = api.Scene(cfg.scene)
-        if name == "config2":
+        if depth == 1:
             views = [(cfg.camera, 16)] + scenegen.orbit_views(77, 3, sizes=((256, 256),), spp=(16,))
         else:
             views = [(cfg.camera.with_window(192, 192, 320, 320), 8)]
@@ -166,6 +166,52 @@ def selection_leg():
     res = _sampler_comparison([(f"M{m}", {"edge_candidates": m}) for m in (4, 16)])
     return {"metric": "gradient variance x time gain (one descent / M-sample selection), 95% bootstrap interval",
             **res}
+
+
+def edge_nee_leg(alpha=0.5):
+    """Next event estimation for edges (the strip strategy mixed in with
+    probability alpha) against the hierarchy alone, secondary term (the only
+    term it changes), 64 seeds per sampler and view, on 4 views of the
+    1,000-triangle scene (256x256, 16 spp, depth 1), the same scene under a
+    0.1 x 0.1 light of the same power, and a 128x128 window of the
+    81,936-triangle depth-3 scene (8 spp). Two measures: the per-seed
+    variance x backward time (as for the other samplers), and the squared
+    error of the 64-seed mean against an independent 128-seed reference of
+    the strip mixture, which also counts what a heavy-tailed sampler's seeds
+    missed."""
+    from paper_1904_12228_amd import api, proposal, scenegen
+
+    scenes = (("config2", scenegen.config2(), 1),
+              ("config2_small_light", scenegen.soup(0, 1000, 256, 256, 16, light_emission=250.0, light_size=0.1), 1),
+              ("config3_window", scenegen.config3(), 3))
+    out = {"metric": f"secondary-term gain (hierarchy / hierarchy mixed with edge strips crossed by segments to "
+                     f"light points, probability {alpha}): variance x time and reference error x time, "
+                     f"95% bootstrap intervals"}
+    for name, cfg, depth in scenes:
+        S = api.Scene(cfg.scene)
+        if depth == 1:
+            views = [(cfg.camera, 16)] + scenegen.orbit_views(77, 3, sizes=((256, 256),), spp=(16,))
+        else:
+            views = [(cfg.camera.with_window(192, 192, 320, 320), 8)]
+        plain, other, refs, covered = [], [], [], [0, 0]
+        for i, (cam, spp) in enumerate(views):
+            G, ta = proposal.gradient_samples(S, cam, spp, depth, [s + 1000 * i for s in range(64)], terms=4)
+            H, tb = proposal.gradient_samples(S, cam, spp, depth, [s + 1000 * i + 500 for s in range(64)], terms=4,
+                                              edge_nee=alpha)
+            R, _ = proposal.gradient_samples(S, cam, spp, depth, [s + 1000 * i + 100000 for s in range(128)],
+                                             terms=4, edge_nee=alpha)
+            plain.append((G, sorted(ta)[len(ta) // 2]))
+            other.append((H, sorted(tb)[len(tb) // 2]))
+            refs.append(R)
+            covered[0] += int(((G != 0).double().mean(0) >= 0.9).sum())
+            covered[1] += int(((H != 0).double().mean(0) >= 0.9).sum())
+        out[name] = {"variance": proposal.variance_time_stats(plain, other),
+                     "reference_error": proposal.reference_error_stats(plain, other, refs),
+                     "entries_nonzero_in_90pct_of_seeds": covered}
+        del plain, other, refs
+        S.close()
+        print(f"edge nee: {name} done", file=sys.stderr, flush=True)
+    return out
 
 
 def gbuffer_leg(S, cam, spp, d_image, reps=3):
@@ -299,6 +345,8 @@ def main():
     ap.add_argument("--no-gbuffer", action="store_true", help="skip the geometry-buffer leg")
     ap.add_argument("--no-selection", action="store_true",
                     help="skip the multi-sample edge selection vs one descent variance x time leg")
+    ap.add_argument("--no-nee", action="store_true",
+                    help="skip the next-event-estimation-for-edges vs hierarchy variance x time leg")
     ap.add_argument("--no-edge-points", action="store_true",
                     help="skip the clamped-cosine vs uniform edge-point variance x time leg")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
@@ -422,6 +470,9 @@ def main():
     if not args.no_selection:
         print("running the edge-selection leg", file=sys.stderr, flush=True)
         out["edge_selection"] = selection_leg()
+    if not args.no_nee:
+        print("running the next-event-estimation-for-edges leg", file=sys.stderr, flush=True)
+        out["edge_nee"] = edge_nee_leg()
     if not args.no_inverse:
         print("running the batched inverse-rendering leg", file=sys.stderr, flush=True)
         out["inverse_rendering"] = inverse_leg()

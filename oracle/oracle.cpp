@@ -1526,7 +1526,12 @@ bool nee_usable(const NeeQuery& q, const V3d& dh, int lt, Unit* U) {
 }
 
 // Density p_N of the billboard strategy at (edge ei, t, sv), in dt ds.
-double nee_pdf(const NeeQuery& q, int ei, double t, double sv, Unit* U) {
+// known_lt: the light triangle of the draw's own light point (-1: none). The
+// ray through the strip point meets that triangle by construction (the strip
+// point lies on the segment to the light point), so its hit is taken without
+// the inside and side tests: a rounding miss there would drop the strategy's
+// own density from the sample's weight.
+double nee_pdf(const NeeQuery& q, int ei, double t, double sv, int known_lt, Unit* U) {
     const Scn& s = *q.s;
     double imp = nee_importance(s, ei, q.p, q.n, q.tri, U);
     if (!(imp > 0) || s.atot <= 0) return 0;
@@ -1538,30 +1543,40 @@ double nee_pdf(const NeeQuery& q, int ei, double t, double sv, Unit* U) {
     double cb = std::fabs(dot(dh, B.nb));
     double acc = 0;
     for (int lt : s.lights) {
-        TriHit h = tri_test(s, lt, q.p, d, 1.0, 1e300);
-        if (!h.valid) continue;
-        if (U && h.t > 1 - kTieLight && std::fabs(h.m) < kTieLight) TIE(*U, 21);
-        if (U && h.m > -kTieLight && std::fabs(h.t - 1) < kTieLight) TIE(*U, 21);
-        if (!h.ok) continue;
-        if (!nee_usable(q, dh, lt, U)) continue;
-        double cy = std::fabs(dot(normalize(s.face_n(lt)), dh));
+        double mu;
+        V3d nl = normalize(s.face_n(lt));
+        if (lt == known_lt) {
+            double dn = dot(d, nl);
+            if (dn == 0) continue;
+            mu = dot(s.p(s.I[3 * lt]) - q.p, nl) / dn;
+        } else {
+            TriHit h = tri_test(s, lt, q.p, d, 1.0, 1e300);
+            if (!h.valid) continue;
+            if (U && h.t > 1 - kTieLight && std::fabs(h.m) < kTieLight) TIE(*U, 21);
+            if (U && h.m > -kTieLight && std::fabs(h.t - 1) < kTieLight) TIE(*U, 21);
+            if (!h.ok) continue;
+            if (!nee_usable(q, dh, lt, U)) continue;
+            mu = h.t;
+        }
+        double cy = std::fabs(dot(nl, dh));
         if (!(cy > 0)) continue;
-        V3d y = q.p + d * h.t;
+        V3d y = q.p + d * mu;
         double sum = imp + nee_crossed_sum(q, y, ei, U);
-        acc += h.t * h.t * cb / cy * imp / sum;
+        acc += mu * mu * cb / cy * imp / sum;
     }
     return acc * B.L / s.atot;
 }
 
 // One draw of the billboard strategy from uniforms ul = (light pick, two
 // point uniforms) and the race uniforms of stream rs (edge e: block 2 + e,
-// first uniform). Returns the edge (or -1) and its strip coordinates.
-int nee_sample(const NeeQuery& q, const double ul[3], const Stream& rs, double& t, double& sv, Unit* U) {
+// first uniform). Returns the edge (or -1), its strip coordinates and the
+// light triangle of the light point.
+int nee_sample(const NeeQuery& q, const double ul[3], const Stream& rs, double& t, double& sv, int& lt, Unit* U) {
     const Scn& s = *q.s;
     if (s.lights.empty()) return -1;
     Unit dummy;
     int li = cdf_pick(s.lcdf, ul[0], U ? *U : dummy);
-    int lt = s.lights[li];
+    lt = s.lights[li];
     V3d a = s.p(s.I[3 * lt]), b = s.p(s.I[3 * lt + 1]), c = s.p(s.I[3 * lt + 2]);
     double su = std::sqrt(ul[1]);
     V3d y = a * (1 - su) + b * (su * (1 - ul[2])) + c * (su * ul[2]);
@@ -1595,10 +1610,10 @@ int nee_mix_draw(const TreeQuery& tq, double w, double alpha, const Stream& rk, 
     rn.block(0, c0);
     rn.block(1, c1);
     if (U && std::fabs(c0[0] - alpha) < kTieU) TIE(*U, 22);
-    int ei;
+    int ei, lt = -1;
     double sv, ph;
     if (c0[0] < alpha) {
-        ei = nee_sample(q, c0 + 1, rn, t, sv, U);
+        ei = nee_sample(q, c0 + 1, rn, t, sv, lt, U);
         if (ei < 0) return -1;
         ph = tree_pdf_edge(tq, ei, U);
     } else {
@@ -1615,7 +1630,7 @@ int nee_mix_draw(const TreeQuery& tq, double w, double alpha, const Stream& rk, 
         t = b0[1];
         sv = (c1[0] - 0.5) * w;
     }
-    pdf = alpha * w * nee_pdf(q, ei, t, sv, U) + (1 - alpha) * ph;
+    pdf = alpha * w * nee_pdf(q, ei, t, sv, lt, U) + (1 - alpha) * ph;
     return pdf > 0 ? ei : -1;
 }
 
@@ -2092,7 +2107,8 @@ int orc_edge_nee_sample(const orc_scene* sd, const double p[3], const double n[3
         rn.block(0, c0);
         Unit U;
         t[i] = sv[i] = 0;
-        edge[i] = nee_sample(q, c0 + 1, rn, t[i], sv[i], &U);
+        int lt;
+        edge[i] = nee_sample(q, c0 + 1, rn, t[i], sv[i], lt, &U);
         if (flags) flags[i] = U.flag;
     }
     return ORC_OK;
@@ -2107,7 +2123,7 @@ int orc_edge_nee_pdf(const orc_scene* sd, const double p[3], const double n[3], 
     NeeQuery q{&s, V3d{p[0], p[1], p[2]}, V3d{n[0], n[1], n[2]}, tri, width};
     for (int i = 0; i < count; ++i) {
         if (edge[i] < 0 || edge[i] >= (int)s.edges.size()) return ORC_EINVAL;
-        pdf[i] = nee_pdf(q, edge[i], t[i], sv[i], nullptr);
+        pdf[i] = nee_pdf(q, edge[i], t[i], sv[i], -1, nullptr);
     }
     return ORC_OK;
 }

@@ -30,6 +30,7 @@ SceneView drScene_t::view() const {
     v.tri = tri.as<float4>();
     v.bvh = bvh.as<BvhNode>();
     v.edges = edges.as<int4>();
+    v.towned = towned.as<int4>();
     v.ekind = ekind.as<uint8_t>();
     v.lights = lights.as<int>();
     v.lcdf = lcdf.as<double>();
@@ -48,7 +49,8 @@ static void release_all(drScene_t* s) {
                    &s->scal, &s->err, &s->codes, &s->ids, &s->codes_s, &s->ids_s, &s->keys64, &s->parent, &s->counter,
                    &s->sort_tmp, &s->pe, &s->plen, &s->pcdf, &s->scan_tmp, &s->ecls, &s->epos, &s->elist, &s->ecode,
                    &s->ecode_s, &s->elist_s, &s->ekeys, &s->eparent, &s->ecounter, &s->etree, &s->ebounds, &s->edepth,
-                   &s->ck_tri, &s->ck_x, &s->ck_vis, &s->camacc};
+                   &s->ck_tri, &s->ck_x, &s->ck_vis, &s->camacc, &s->mixw, &s->mcdf, &s->qcdf, &s->eleaf,
+                   &s->enpar, &s->towned};
     for (Buf* b : bufs) b->release();
     for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount, &s->svtri, &s->svx, &s->pq, &s->pcount}) b->release();
     s->counters.release();
@@ -178,6 +180,14 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
         edges.push_back(make_int4(ks[i].a, ks[i].b, ks[i].f, j - i == 2 ? ks[i + 1].f : -1));
         i = j;
     }
+    // per triangle, the edges it is the first face of (each edge once)
+    std::vector<int4> towned((size_t)T, make_int4(-1, -1, -1, -1));
+    for (size_t i = 0; i < edges.size(); ++i) {
+        int4& o = towned[(size_t)edges[i].z];
+        if (o.x < 0) o.x = (int)i;
+        else if (o.y < 0) o.y = (int)i;
+        else o.z = (int)i;
+    }
     std::vector<int> lights;
     for (int t = 0; t < T; ++t)
         if (emi[t] > 0.0f) lights.push_back(t);
@@ -223,6 +233,7 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     TRY_ALLOC(s->tri, sizeof(float4) * 3 * T);
     TRY_ALLOC(s->bvh, sizeof(BvhNode) * std::max(T - 1, 1));
     TRY_ALLOC(s->edges, sizeof(int4) * s->E);
+    TRY_ALLOC(s->towned, sizeof(int4) * T);
     TRY_ALLOC(s->ekind, std::max(s->E, 1));
     TRY_ALLOC(s->lights, sizeof(int) * std::max(s->L, 1));
     TRY_ALLOC(s->lcdf, sizeof(double) * std::max(s->L, 1));
@@ -242,6 +253,7 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
         hipMemcpyAsync(s->alb.p, d->albedo, sizeof(float) * T, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(s->emi.p, d->emission, sizeof(float) * T, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(s->edges.p, edges.data(), sizeof(int4) * s->E, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->towned.p, towned.data(), sizeof(int4) * T, hipMemcpyHostToDevice, st) != hipSuccess ||
         (s->L && hipMemcpyAsync(s->lights.p, lights.data(), sizeof(int) * s->L, hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipMemsetAsync(s->err.p, 0, sizeof(int), st) != hipSuccess)
         return fail(DR_ERROR_DEVICE);

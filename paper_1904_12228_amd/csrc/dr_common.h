@@ -117,6 +117,7 @@ struct SceneView {
     const float4* tri;       // [T][3] v0.xyz e1.x | e1.yz e2.xy | e2.z - - -
     const BvhNode* bvh;      // [T-1] (T == 1: unused)
     const int4* edges;       // [E] va, vb, f0, f1
+    const int4* towned;      // [T] up to three edges whose first face is the triangle, -1 padded
     const uint8_t* ekind;    // [E] 0 never, 1 always, 2 silhouette-only
     const int* lights;       // [L]
     const double* lcdf;      // [L]

@@ -60,6 +60,7 @@ struct drScene_t {
     uint64_t version = 0;            // bumps on every vertex update
     // scene data
     dr::Buf P, I, N, alb, emi, tri, bvh, edges, ekind, lights, lcdf, scal, err;
+    dr::Buf towned;                  // [T] int4: edges whose first face is the triangle (-1: none)
     // BVH build scratch
     dr::Buf codes, ids, codes_s, ids_s, keys64, parent, counter, sort_tmp;
     // host side of the SAH build: indices (kept from creation), vertex copy,

@@ -949,7 +949,7 @@ __device__ inline float cosine_edge_pdf(v3 p, v3 n, v3 pa, v3 pb, float t, float
 // pa - x; among the strips the segment x -> y crosses, one is chosen in
 // proportion to the edge's importance (an exponential race: edge e's key
 // -log(1 - u_e) / imp_e with u_e from its own Philox block, the smallest key
-// wins, so the choice does not depend on the order of the hierarchy walk
+// wins, so the choice does not depend on the order of the BVH walk
 // that finds the crossings), and the crossing's parameter t is the point on
 // the edge. Its density in (t, s): the ray from x through the strip point b
 // meets the lights at y = x + mu (b - x), mu > 1, each drawn with area
@@ -1015,61 +1015,76 @@ __device__ inline float strip_importance(const SceneView& s, int ei, const TreeC
     return len(b - a) * cb * rsqrtf(dot(dc, dc));
 }
 
-// Segment x -> x + d (parameter in [0, 1]) against a box grown by pad. A zero
-// direction component on the box's boundary gives NaN bounds, which fminf /
-// fmaxf ignore: the test then errs towards a visit.
-__device__ inline bool seg_box(const float* lo, const float* hi, float pad, v3 x, v3 inv) {
-    float t0 = 0.0f, t1 = 1.0f;
-    const float xv[3] = {x.x, x.y, x.z}, iv[3] = {inv.x, inv.y, inv.z};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        float a = (lo[k] - pad - xv[k]) * iv[k], b = (hi[k] + pad - xv[k]) * iv[k];
-        t0 = fmaxf(t0, fminf(a, b));
-        t1 = fminf(t1, fmaxf(a, b));
-    }
+// Segment x -> x + d (parameter in [0, 1]) against a box grown by pad (inv:
+// the reciprocals of d's components). A zero component of d on a grown face
+// gives NaN, which fminf / fmaxf drop; such a segment lies outside the
+// ungrown box by the pad's margin beyond the strip, so the test cannot lose
+// a crossing either way.
+__device__ inline bool seg_box(v3 x, v3 inv, float pad, float lx, float ly, float lz, float hx, float hy, float hz) {
+    float a0 = (lx - pad - x.x) * inv.x, b0 = (hx + pad - x.x) * inv.x;
+    float a1 = (ly - pad - x.y) * inv.y, b1 = (hy + pad - x.y) * inv.y;
+    float a2 = (lz - pad - x.z) * inv.z, b2 = (hz + pad - x.z) * inv.z;
+    float t0 = fmaxf(fmaxf(fminf(a0, b0), fminf(a1, b1)), fmaxf(fminf(a2, b2), 0.0f));
+    float t1 = fminf(fminf(fmaxf(a0, b0), fmaxf(a1, b1)), fminf(fmaxf(a2, b2), 1.0f));
     return t0 <= t1;
 }
 
-// Visits every edge whose hierarchy box, grown by pad, meets the segment
-// x -> x + d: depth first, child 0 first, without a stack (the parent links
-// lead back up; every node is entered once and left twice).
+// Visits every edge of the triangles whose BVH boxes, grown by pad, meet the
+// segment x -> x + d (a strip lies within half its width of its edge, and an
+// edge within its faces' boxes); each edge once, through its first face.
+// stk: this lane's LDS stack (entries `stride` words apart, s.stk_cap of
+// them), as the ray traversals use it.
 template <class F, class W>
-__device__ inline void strip_walk(const SceneView& s, const TreeView& tv, v3 x, v3 d, float pad, W& wk, F&& visit) {
+__device__ inline void strip_walk(const SceneView& s, v3 x, v3 d, float pad, int* stk, int stride, W& wk, F&& visit) {
+    auto leaf = [&](int tr) {
+        int4 o = s.towned[tr];
+        if (o.x >= 0) visit(o.x);
+        if (o.y >= 0) visit(o.y);
+        if (o.z >= 0) visit(o.z);
+    };
+    if (s.T == 1) {
+        leaf(0);
+        return;
+    }
     v3 inv = {1.0f / d.x, 1.0f / d.y, 1.0f / d.z};
-    int node = 0, c = 0;
-    for (long guard = 6L * s.E + 8; guard > 0; --guard) {
-        if (c < 2) {
-            const ETNode* N = tv.nodes + node;
-            int ref = N->child[c];
-            if (ref != 0) {
-                wk.tree();
-                if (seg_box(N->ch[c].lo, N->ch[c].hi, pad, x, inv)) {
-                    if (ref > 0) {
-                        node = ref;
-                        c = 0;
-                        continue;
-                    }
-                    visit(~ref);
-                }
-            }
-            ++c;
+    int sp = 0, node = 0;
+    for (int guard = 2 * s.T + 8; guard > 0; --guard) {
+        wk.tree();
+        BvhNode n = load_bvh(s.bvh, node);
+        bool hl = seg_box(x, inv, pad, n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y);
+        bool hr = seg_box(x, inv, pad, n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w);
+        int l = n.d.x, r = n.d.y;
+        if (hl && l < 0) {
+            leaf(~l);
+            hl = false;
+        }
+        if (hr && r < 0) {
+            leaf(~r);
+            hr = false;
+        }
+        if (hl && hr) {
+            if (sp < s.stk_cap) stk[(sp++) * stride] = r;
+            else atomicOr(s.err, kErrStack);
+            node = l;
+        } else if (hl) {
+            node = l;
+        } else if (hr) {
+            node = r;
         } else {
-            if (node == 0) return;
-            int pc = tv.enpar[node];
-            node = pc >> 1;
-            c = (pc & 1) + 1;
+            if (sp == 0) return;
+            node = stk[(--sp) * stride];
         }
     }
-    atomicOr(s.err, kErrTreeDepth);
+    atomicOr(s.err, kErrStack);
 }
 
 // Sum of the importances of the strips crossed by x -> y, edge `skip` left out.
 template <class W>
-__device__ inline float strip_crossed_sum(const SceneView& s, const TreeView& tv, const TreeCtx& q, float w, v3 y,
-                                          int skip, W& wk) {
+__device__ inline float strip_crossed_sum(const SceneView& s, const TreeCtx& q, float w, v3 y, int skip, int* stk,
+                                          int stride, W& wk) {
     float sum = 0.0f;
     v3 d = y - q.p;
-    strip_walk(s, tv, q.p, d, kStripPad * w + kWalkPad * s.diag, wk, [&](int ei) {
+    strip_walk(s, q.p, d, kStripPad * w + kWalkPad * s.diag, stk, stride, wk, [&](int ei) {
         if (ei == skip) return;
         float t, sv;
         if (!strip_cross(strip_of(s, s.edges[ei], q.p), q.p, d, w, t, sv)) return;
@@ -1086,10 +1101,16 @@ __device__ inline bool strip_light_usable(const SceneView& s, const TreeCtx& q, 
     return -dot(nrm(cross(g.e1, g.e2)), dh) > 0.0f;
 }
 
-// Density of the strip strategy at (edge ei, t, sv), in dt ds.
+// Density of the strip strategy at (edge ei, t, sv), in dt ds. known_lt /
+// known_sum: the light triangle of the draw's own light point (-1: none) and
+// the crossed-importance sum along the segment to it. The ray through the
+// strip point meets that triangle by construction, at the light point up to
+// rounding, so its hit is taken without the inside and side tests (a rounding
+// miss would drop the strategy's own density from the sample's weight) and
+// the sum is not walked again.
 template <class W>
-__device__ inline float strip_pdf(const SceneView& s, const TreeView& tv, const TreeCtx& q, float w, int ei, float t,
-                                  float sv, W& wk) {
+__device__ inline float strip_pdf(const SceneView& s, const TreeCtx& q, float w, int ei, float t, float sv, int known_lt,
+                                  float known_sum, int* stk, int stride, W& wk) {
     float imp = strip_importance(s, ei, q);
     if (!(imp > 0.0f) || s.L == 0) return 0.0f;
     Strip B = strip_of(s, s.edges[ei], q.p);
@@ -1100,22 +1121,31 @@ __device__ inline float strip_pdf(const SceneView& s, const TreeView& tv, const 
     float cb = fabsf(dot(dh, B.nb));
     float acc = 0.0f;
     for (int i = 0; i < s.L; ++i) {
-        TriGeom g = tri_geom(s, s.lights[i]);
-        // Moller-Trumbore on the ray x + mu d, both faces, mu > 1
-        v3 pv = cross(d, g.e2);
-        float det = dot(g.e1, pv);
-        if (det == 0.0f) continue;
-        float inv = 1.0f / det;
-        v3 tq = q.p - g.p0;
-        float u = dot(tq, pv) * inv;
-        v3 qv = cross(tq, g.e1);
-        float vv = dot(d, qv) * inv;
-        float mu = dot(g.e2, qv) * inv;
-        if (!(u >= 0.0f && vv >= 0.0f && u + vv <= 1.0f && mu > 1.0f)) continue;
-        if (!strip_light_usable(s, q, dh, g)) continue;
-        float cy = fabsf(dot(nrm(cross(g.e1, g.e2)), dh));
+        int lt = s.lights[i];
+        TriGeom g = tri_geom(s, lt);
+        v3 nl = nrm(cross(g.e1, g.e2));
+        float mu;
+        if (lt == known_lt) {
+            float dn = dot(d, nl);
+            if (dn == 0.0f) continue;
+            mu = dot(g.p0 - q.p, nl) / dn;
+        } else {
+            // Moller-Trumbore on the ray x + mu d, both faces, mu > 1
+            v3 pv = cross(d, g.e2);
+            float det = dot(g.e1, pv);
+            if (det == 0.0f) continue;
+            float inv = 1.0f / det;
+            v3 tq = q.p - g.p0;
+            float u = dot(tq, pv) * inv;
+            v3 qv = cross(tq, g.e1);
+            float vv = dot(d, qv) * inv;
+            mu = dot(g.e2, qv) * inv;
+            if (!(u >= 0.0f && vv >= 0.0f && u + vv <= 1.0f && mu > 1.0f)) continue;
+            if (!strip_light_usable(s, q, dh, g)) continue;
+        }
+        float cy = fabsf(dot(nl, dh));
         if (!(cy > 0.0f)) continue;
-        float sum = imp + strip_crossed_sum(s, tv, q, w, q.p + d * mu, ei, wk);
+        float sum = lt == known_lt ? known_sum : imp + strip_crossed_sum(s, q, w, q.p + d * mu, ei, stk, stride, wk);
         acc += mu * mu * cb / cy * imp / sum;
     }
     return acc * B.L / s.atot[0];
@@ -1123,12 +1153,13 @@ __device__ inline float strip_pdf(const SceneView& s, const TreeView& tv, const 
 
 // One draw of the strip strategy: light point from c0.y (light), c0.z, c0.w
 // (point), the race's uniforms from rn's blocks 2 + edge id. Returns the
-// edge (or -1) and the crossing's strip coordinates.
+// edge (or -1), the crossing's strip coordinates, the light triangle and the
+// sum of the crossed strips' importances.
 template <class W>
-__device__ inline int strip_sample(const SceneView& s, const TreeView& tv, const TreeCtx& q, float w, float4 c0,
-                                   const Rng& rn, float& t, float& sv, W& wk) {
+__device__ inline int strip_sample(const SceneView& s, const TreeCtx& q, float w, float4 c0, const Rng& rn, float& t,
+                                   float& sv, int& lt, float& sum, int* stk, int stride, W& wk) {
     if (s.L == 0) return -1;
-    int lt = s.lights[pick_cdf(s.lcdf, s.L, c0.y)];
+    lt = s.lights[pick_cdf(s.lcdf, s.L, c0.y)];
     TriGeom g = tri_geom(s, lt);
     float su = sqrtf(c0.z);
     v3 y = g.p0 + g.e1 * (su * (1.0f - c0.w)) + g.e2 * (su * c0.w);
@@ -1136,11 +1167,13 @@ __device__ inline int strip_sample(const SceneView& s, const TreeView& tv, const
     if (!strip_light_usable(s, q, nrm(d), g)) return -1;
     int best = -1;
     float kbest = 3e38f;
-    strip_walk(s, tv, q.p, d, kStripPad * w + kWalkPad * s.diag, wk, [&](int ei) {
+    sum = 0.0f;
+    strip_walk(s, q.p, d, kStripPad * w + kWalkPad * s.diag, stk, stride, wk, [&](int ei) {
         float te, se;
         if (!strip_cross(strip_of(s, s.edges[ei], q.p), q.p, d, w, te, se)) return;
         float imp = strip_importance(s, ei, q);
         if (!(imp > 0.0f)) return;
+        sum += imp;
         float key = -logf(1.0f - rn.block(2u + (uint32_t)ei).x) / imp;
         if (key < kbest) {
             kbest = key;
@@ -1157,13 +1190,14 @@ __device__ inline int strip_sample(const SceneView& s, const TreeView& tv, const
 // -1), its parameter t and the density in (e, t).
 template <class W>
 __device__ inline int strip_mix_draw(const SceneView& s, const TreeView& tv, const TreeCtx& q, const RenderArgs& a,
-                                     const Rng& rk, float4 b0, const Rng& rn, float& t, float& pdf, W& wk) {
+                                     const Rng& rk, float4 b0, const Rng& rn, float& t, float& pdf, int* stk, int stride,
+                                     W& wk) {
     float4 c0 = rn.block(0);
     float w = a.nee_w;
-    int ei;
-    float sv, ph;
+    int ei, lt = -1;
+    float sv, ph, sum = 0.0f;
     if (c0.x < a.nee) {
-        ei = strip_sample(s, tv, q, w, c0, rn, t, sv, wk);
+        ei = strip_sample(s, q, w, c0, rn, t, sv, lt, sum, stk, stride, wk);
         if (ei < 0) return -1;
         ph = tree_pdf_edge(tv, q, ei, wk);
     } else {
@@ -1172,7 +1206,7 @@ __device__ inline int strip_mix_draw(const SceneView& s, const TreeView& tv, con
         t = b0.y;
         sv = (rn.block(1).x - 0.5f) * w;
     }
-    pdf = a.nee * w * strip_pdf(s, tv, q, w, ei, t, sv, wk) + (1.0f - a.nee) * ph;
+    pdf = a.nee * w * strip_pdf(s, q, w, ei, t, sv, lt, sum, stk, stride, wk) + (1.0f - a.nee) * ph;
     return pdf > 0.0f ? ei : -1;
 }
 
@@ -1556,8 +1590,10 @@ __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderA
                                                      int nvert, MixArgs mx) {
     // no rays are traced here: no traversal stack (STK only names the variant);
     // SEL: the multi-sample edge selection and its LDS stack of deferred children;
-    // NEE: the strip strategy (next event estimation for edges) mixed with the hierarchy
+    // NEE: the strip strategy (next event estimation for edges) mixed with the
+    // hierarchy, and the LDS stack of its walks through the triangle BVH
     __shared__ int sel_stk[SEL ? kSelectMax * 4 * BS : 1];
+    __shared__ int walk_stk[NEE ? STK * BS : 1];
     int lane = threadIdx.x;
     NoWork wk;
     long item = (long)blockIdx.x * BS + lane;
@@ -1614,7 +1650,7 @@ __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderA
             do {
                 if (NEE) {
                     Rng rn{sid, a.view, kTagEnee + (uint32_t)(kk + 1), a.k0, a.k1};
-                    ei = strip_mix_draw(s, tv, q, a, rk, b0, rn, te_draw, pdf, wk);
+                    ei = strip_mix_draw(s, tv, q, a, rk, b0, rn, te_draw, pdf, walk_stk + lane, BS, wk);
                 } else if (MIX && mx.sec) {
                     // proposal mixture: component from the third uniform of the
                     // block, proposal draw from the fourth

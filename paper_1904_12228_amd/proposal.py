@@ -138,7 +138,7 @@ class EdgeProposal:
 
 
 def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mix=0.0, mix_terms=0,
-                           d_image=1.0, terms=0, edge_t=0, edge_candidates=0):
+                           d_image=1.0, terms=0, edge_t=0, edge_candidates=0, edge_nee=0.0):
     """Sum over vertex-gradient entries of the variance of the estimate across
     seeds, the mean gradient, and the mean time of one drRenderBackward (HIP
     events around the call, forward checkpoints excluded)."""
@@ -156,7 +156,7 @@ def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=No
         e0.record(st)
         scene.render_backward(cam, spp, depth, dimg, seed=sd, terms=terms, want=("vertices",), outs=(dv, None, None),
                               edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t,
-                              edge_candidates=edge_candidates)
+                              edge_candidates=edge_candidates, edge_nee=edge_nee)
         e1.record(st)
         e1.synchronize()
         ms += e0.elapsed_time(e1)
@@ -170,7 +170,7 @@ def gradient_variance_time(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=No
 
 
 def gradient_samples(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mix=0.0, mix_terms=0, d_image=1.0,
-                     terms=0, edge_t=0, edge_candidates=0):
+                     terms=0, edge_t=0, edge_candidates=0, edge_nee=0.0):
     """Per-seed vertex gradients [len(seeds), 3V] (float64, device) and the
     drRenderBackward duration of each seed in ms (HIP events around the call,
     forward checkpoints excluded)."""
@@ -187,7 +187,7 @@ def gradient_samples(scene: api.Scene, cam, spp, depth, seeds, edge_pdf=None, mi
         e0.record(st)
         scene.render_backward(cam, spp, depth, dimg, seed=sd, terms=terms, want=("vertices",), outs=(dv, None, None),
                               edge_pdf=edge_pdf, edge_mix=mix, edge_mix_terms=mix_terms, edge_t=edge_t,
-                              edge_candidates=edge_candidates)
+                              edge_candidates=edge_candidates, edge_nee=edge_nee)
         e1.record(st)
         e1.synchronize()
         ms.append(e0.elapsed_time(e1))
@@ -233,6 +233,37 @@ def variance_time_stats(plain, other, n_boot=500, seed=0):
         total += int(ok.sum())
     return {"var_plain": vp, "var_other": vo, "ms_plain": tp, "ms_other": to, "gain": gain,
             "gain_ci95": [lo, hi], "welch_beyond_4se": beyond, "welch_entries": total}
+
+
+def reference_error_stats(plain, other, refs, n_boot=500, seed=0):
+    """Squared error of each sampler's seed-averaged gradient against an
+    independent reference of the same expectation. plain / other: lists (one
+    per view) of (samples [K, N], time_ms); refs: per view, reference samples
+    [R, N] from seeds neither sampler used. Per sampler, err = K x (sum over
+    views and entries of (mean over its K seeds - reference mean)^2 minus the
+    reference mean's own variance): an estimate of the per-seed variance that
+    also charges a heavy-tailed sampler for the contributions its seeds
+    missed (the sample variance around the sample's own mean does not).
+    Returns both errors, the gain err_plain t_plain / (err_other t_other)
+    and a bootstrap 95% interval (the samplers' seeds resampled, the
+    reference held fixed)."""
+    def err(pairs, idx_fn=None):
+        tot = 0.0
+        for (G, _), R in zip(pairs, refs):
+            X = G if idx_fn is None else G[idx_fn(G.shape[0])]
+            rm = R.mean(0)
+            tot += X.shape[0] * (float(((X.mean(0) - rm) ** 2).sum()) - float(R.var(0).sum()) / R.shape[0])
+        return tot
+
+    ep, eo = err(plain), err(other)
+    tp = sum(t for _, t in plain) / len(plain)
+    to = sum(t for _, t in other) / len(other)
+    gain = (ep * tp) / (eo * to) if eo * to > 0 else float("nan")
+    gen = torch.Generator(device=plain[0][0].device).manual_seed(seed)
+    pick = lambda K: torch.randint(0, K, (K,), device=plain[0][0].device, generator=gen)
+    boots = sorted((err(plain, pick) * tp) / (err(other, pick) * to) for _ in range(n_boot))
+    lo, hi = boots[int(0.025 * n_boot)], boots[int(0.975 * n_boot) - 1]
+    return {"err_plain": ep, "err_other": eo, "ms_plain": tp, "ms_other": to, "gain": gain, "gain_ci95": [lo, hi]}
 
 
 def seconds() -> float:
