@@ -168,7 +168,7 @@ def selection_leg():
             **res}
 
 
-def edge_nee_leg(alpha=0.5):
+def edge_nee_leg(alpha=0.25):
     """Next event estimation for edges (the strip strategy mixed in with
     probability alpha) against the hierarchy alone, secondary term (the only
     term it changes), 64 seeds per sampler and view, on 4 views of the
