@@ -52,7 +52,9 @@ static void release_all(drScene_t* s) {
                    &s->ck_tri, &s->ck_x, &s->ck_vis, &s->camacc, &s->mixw, &s->mcdf, &s->qcdf, &s->eleaf,
                    &s->enpar, &s->towned};
     for (Buf* b : bufs) b->release();
-    for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount, &s->svtri, &s->svx, &s->pq, &s->pcount}) b->release();
+    for (Buf* b : {&s->sq, &s->sres, &s->sqidx, &s->scount, &s->svtri, &s->svx, &s->pq, &s->pcount, &s->fq, &s->fcount,
+                   &s->fL})
+        b->release();
     s->counters.release();
     for (auto& e : s->evs) {
         (void)hipEventDestroy(e.a);
@@ -201,6 +203,7 @@ drStatus drSceneCreate(drScene* out, const drSceneDesc* d, hipStream_t st) {
     s->background = d->background;
     if (const char* e = std::getenv("DIFFRT_SPLIT_BACKWARD")) s->split_backward = std::atoi(e) != 0;
     if (const char* e = std::getenv("DIFFRT_SPLIT_PRIMARY")) s->split_primary = std::atoi(e) != 0;
+    if (const char* e = std::getenv("DIFFRT_WAVEFRONT_FORWARD")) s->wavefront_forward = std::atoi(e) != 0;
     // triangle BVH topology: binned SAH on the host (default) or Morton-code LBVH on the device
     if (const char* e = std::getenv("DIFFRT_BVH")) s->sah_bvh = std::strcmp(e, "lbvh") != 0;
     s->hI = I;

@@ -91,6 +91,11 @@ struct drScene_t {
     bool split_backward = true;
     dr::Buf pq, pcount;              // primary edge samples whose sides hit different triangles
     bool split_primary = true;
+    // wavefront forward (DIFFRT_WAVEFRONT_FORWARD=1): per-bounce queues, their
+    // counts, unit radiance; off by default (18.3 ms against the single
+    // kernel's 15.2 ms at config 3)
+    dr::Buf fq, fcount, fL;
+    bool wavefront_forward = false;
     hipStream_t last_stream = nullptr;
     int device = 0;
     // measurement

@@ -145,6 +145,170 @@ __global__ __launch_bounds__(BS, 6) void k_forward(SceneView s, Cam k, RenderArg
     forward_body<STK, CNT>(s, k, a, image, reduce, blockIdx.x * BS, stk);
 }
 
+// ---------------------------------------------------------------------------
+// Wavefront forward (max_depth 2 or 3): the camera paths of k_forward split
+// at their continuation rays. k_fwd_hit traces every camera ray, does the
+// first vertex's next-event estimation, stores the first checkpoint and, for
+// the paths that continue, appends (unit, direction) to the queue of bounce 1
+// (wave ballot + popcount, one atomic per wave). k_fwd_bounce<k> drains the
+// queue of bounce k on a persistent grid: it traces the continuation ray
+// from checkpoint k - 1, stores checkpoint k, adds vertex k + 1's
+// next-event estimation to the unit's radiance and queues the next bounce.
+// Every unit's arithmetic is k_forward's, step for step (beta is rebuilt as
+// the same product of checkpointed albedos), so radiance, checkpoints and
+// visibility bits are bit-identical; k_fwd_image reduces the radiance to
+// pixels as k_forward does.
+// ---------------------------------------------------------------------------
+struct FwdQueue {
+    int4* q;        // [2][M]: unit, direction bits (bounce k at offset (k - 1) M)
+    int* count;     // [2]
+    float* L;       // [M] radiance of each unit
+};
+
+__device__ inline void fwd_push(const FwdQueue& fq, int M, int k, bool push, int m, v3 w) {
+    int lane = threadIdx.x;
+    unsigned long long bal = __ballot(push);
+    if (!bal) return;
+    int leader = __ffsll(bal) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&fq.count[k - 1], __popcll(bal));
+    base = __shfl(base, leader, BS);
+    if (push)
+        fq.q[(size_t)(k - 1) * M + base + __popcll(bal & ((1ull << lane) - 1ull))] =
+            make_int4(m, __float_as_int(w.x), __float_as_int(w.y), __float_as_int(w.z));
+}
+
+// Next-event estimation at path vertex kk (x on triangle tri, facing ns), and
+// the continuation direction when kk < depth; returns whether the path goes
+// on (k_forward's loop body up to its continuation ray).
+template <class W>
+__device__ inline bool fwd_vertex(const SceneView& s, const RenderArgs& a, const Rng& rc, int kk, int tri, v3 x, v3 ns,
+                                  float beta, float& L, uint8_t& vis, v3& w, int* my, W& wk) {
+    float rho = s.alb[tri];
+    if (rho == 0.0f) return false;
+    NeeSample q = nee_sample(s, rc.block(2 * kk - 1), x, ns);
+    if (q.K > 0.0f && !trace_any(s, x, q.w, s.tmin, q.r * (1.0f - kShadowEnd), my, BS, wk)) {
+        L += beta * rho * dot(ns, q.w) * q.K;
+        vis |= (uint8_t)(1u << (kk - 1));
+    }
+    if (kk == a.depth) return false;
+    float4 ub = rc.block(2 * kk);
+    w = cosine_dir(ns, ub.x, ub.y);
+    return dot(ns, w) > 0.0f;
+}
+
+template <int STK>
+__global__ __launch_bounds__(BS, 6) void k_fwd_hit(SceneView s, Cam k, RenderArgs a, FwdQueue fq) {
+    __shared__ int stk[STK * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    int m = blockIdx.x * BS + lane;
+    NoWork wk;
+    bool push = false;
+    v3 w = {0, 0, 0};
+    if (m < a.M) {
+        int pix, px, py;
+        uint32_t sid;
+        unit_pixel(k, a, m, pix, px, py, sid);
+        float L = 0.0f;
+        uint8_t vis = 0;
+        int ckt0 = -1;
+        v3 ckx0 = {0, 0, 0};
+        if (!a.mask || a.mask[m]) {
+            Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
+            float4 j = rc.block(0);
+            v3 d = cam_dir(k, px + j.x, py + j.y);
+            Hit h = trace_closest(s, k.c, d, k.nearc, 3.0e38f, my, BS, wk);
+            if (h.tri < 0) {
+                L = s.background;
+            } else {
+                TriGeom g = tri_geom(s, h.tri);
+                v3 x = hit_point(g, k.c, d);
+                bool front = dot(d, cross(g.e1, g.e2)) < 0.0f;
+                L = emitted(s, h.tri, front);
+                ckt0 = h.tri;
+                ckx0 = x;
+                v3 ns = shading_normal(s, h.tri, g, x);
+                if (!front) ns = -ns;
+                push = fwd_vertex(s, a, rc, 1, h.tri, x, ns, 1.0f, L, vis, w, my, wk);
+            }
+        }
+        a.ck_tri[m] = ckt0;
+        a.ck_tri[a.M + m] = -1;
+        a.ck_tri[2 * (size_t)a.M + m] = -1;
+        float* cx = a.ck_x + 3 * (size_t)m;
+        cx[0] = ckx0.x; cx[1] = ckx0.y; cx[2] = ckx0.z;
+        float* cy = a.ck_x + 3 * ((size_t)a.M + m);
+        cy[0] = 0.0f; cy[1] = 0.0f; cy[2] = 0.0f;
+        float* cz = a.ck_x + 3 * (2 * (size_t)a.M + m);
+        cz[0] = 0.0f; cz[1] = 0.0f; cz[2] = 0.0f;
+        a.ck_vis[m] = vis;
+        fq.L[m] = L;
+    }
+    fwd_push(fq, a.M, 1, push, m, w);
+}
+
+template <int STK, int K>
+__global__ __launch_bounds__(BS, 6) void k_fwd_bounce(SceneView s, Cam k, RenderArgs a, FwdQueue fq) {
+    __shared__ int stk[STK * BS];
+    int lane = threadIdx.x;
+    int* my = stk + lane;
+    NoWork wk;
+    int n = fq.count[K - 1];
+    for (int base = blockIdx.x * BS; base < n; base += gridDim.x * BS) {
+        bool in = base + lane < n;
+        bool push = false;
+        int m = 0;
+        v3 w = {0, 0, 0};
+        if (in) {
+            int4 e = fq.q[(size_t)(K - 1) * a.M + base + lane];
+            m = e.x;
+            v3 d = {__int_as_float(e.y), __int_as_float(e.z), __int_as_float(e.w)};
+            const float* cp = a.ck_x + 3 * ((size_t)(K - 1) * a.M + m);
+            v3 x = {cp[0], cp[1], cp[2]};
+            Hit h = trace_closest(s, x, d, s.tmin, 3.0e38f, my, BS, wk);
+            if (h.tri >= 0) {
+                // the albedos of the vertices left so far, multiplied in path order
+                float beta = 1.0f;
+                for (int j = 0; j < K; ++j) beta *= s.alb[a.ck_tri[(size_t)j * a.M + m]];
+                TriGeom g = tri_geom(s, h.tri);
+                v3 x2 = hit_point(g, x, d);
+                bool front = dot(d, cross(g.e1, g.e2)) < 0.0f;
+                a.ck_tri[(size_t)K * a.M + m] = h.tri;
+                float* cq = a.ck_x + 3 * ((size_t)K * a.M + m);
+                cq[0] = x2.x; cq[1] = x2.y; cq[2] = x2.z;
+                int pix, px, py;
+                uint32_t sid;
+                unit_pixel(k, a, m, pix, px, py, sid);
+                Rng rc{sid, a.view, kTagCam, a.k0, a.k1};
+                v3 ns = shading_normal(s, h.tri, g, x2);
+                if (!front) ns = -ns;
+                float L = fq.L[m];
+                uint8_t vis = a.ck_vis[m];
+                push = fwd_vertex(s, a, rc, K + 1, h.tri, x2, ns, beta, L, vis, w, my, wk);
+                fq.L[m] = L;
+                a.ck_vis[m] = vis;
+            }
+        }
+        if (K + 1 < 3) fwd_push(fq, a.M, K + 1, push, m, w);
+    }
+}
+
+// Pixels from the units' radiance, as k_forward ends.
+static __global__ __launch_bounds__(BS) void k_fwd_image(RenderArgs a, const float* __restrict__ L,
+                                                         float* __restrict__ image, int reduce) {
+    int lane = threadIdx.x;
+    int m = blockIdx.x * BS + lane;
+    int pix = m / a.spp;
+    float v = (m < a.M ? L[m] : 0.0f) / (float)a.spp;
+    if (reduce) {
+        for (int off = a.spp >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, BS);
+        if (m < a.M && (lane % a.spp) == 0) image[pix] = v;
+    } else if (m < a.M) {
+        atomicAdd(&image[pix], v);
+    }
+}
+
 // Geometry buffers (Ch. 5, Results): channel a.aov (1..7) of the first hit of
 // each camera ray, or all seven (a.aov = 8; image [7][Hw][Ww]); 0 where the
 // ray escapes. Stores the first-hit checkpoint the backward pass reuses.

@@ -113,3 +113,33 @@ def test_sah_and_morton_bvh_give_the_same_results(monkeypatch):
     np.testing.assert_allclose(res[0][0], res[1][0], rtol=1e-6, atol=1e-7)
     for a, b in zip(res[0][1:], res[1][1:]):
         np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("depth,masked", [(2, False), (3, False), (3, True)])
+def test_wavefront_forward_matches_the_single_kernel(monkeypatch, depth, masked):
+    """The wavefront forward (camera hits, then one compacted queue per
+    bounce) against the single-kernel forward: bit-identical images, and the
+    checkpoints they leave give the same gradients."""
+    from paper_1904_12228_amd import api
+    cfg = sg.sphere_box(seed=2, level=3, width=64, height=48, spp=4, max_depth=3)
+    cam = cfg.camera.with_window(3, 5, 61, 44)
+    x0, y0, x1, y1 = cam.win()
+    M = (x1 - x0) * (y1 - y0) * 4
+    mask = None
+    if masked:
+        mask = torch.as_tensor((np.random.default_rng(1).uniform(size=M) < 0.7).astype(np.uint8), device="cuda")
+    dimg = torch.as_tensor(np.random.default_rng(3).normal(size=(y1 - y0, x1 - x0)), dtype=torch.float32, device="cuda")
+    out = {}
+    for wf in ("1", "0"):
+        monkeypatch.setenv("DIFFRT_WAVEFRONT_FORWARD", wf)
+        print(f"case: wavefront={wf} depth={depth} masked={masked}", flush=True)
+        S = api.Scene(cfg.scene)
+        img = S.render(cam, 4, depth, seed=7, unit_mask=mask)
+        dv, da, dc = S.render_backward(cam, 4, depth, dimg, seed=7, unit_mask=mask)
+        torch.cuda.synchronize()
+        assert not S.device_error()
+        out[wf] = [t.cpu().numpy() for t in (img, dv, da, dc)]
+        S.close()
+    assert np.array_equal(out["1"][0], out["0"][0])
+    for a, b in zip(out["1"][1:], out["0"][1:]):
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * max(np.abs(b).max(), 1e-30))
