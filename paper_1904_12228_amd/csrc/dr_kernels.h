@@ -1552,6 +1552,10 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     v3 wh = w * (1.0f / wl);
                     v3 wp = nrm(wh + nh * kEps3), wm = nrm(wh - nh * kEps3);
                     int rem = a.depth - (kk + 1);
+                    // no bounce left and no light along either side: both
+                    // radiances are zero, and so is the sample
+                    if (PH != 2 && rem == 0 && !may_reach_light(s, p, wp, s.tmin) && !may_reach_light(s, p, wm, s.tmin))
+                        break;
                     float Lp, Lm;
                     if (PH == 1) {
                         // queue the side paths: one atomic per wave
@@ -1854,6 +1858,10 @@ __global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderA
                 v3 nh = c * (1.0f / cn);
                 v3 wh = w * (1.0f / len(w));
                 v3 wp = nrm(wh + nh * kEps3), wm = nrm(wh - nh * kEps3);
+                // the last vertex's side paths end at their first hit: with no
+                // light along either side, both radiances and the sample are zero
+                if (kk + 1 == a.depth && !may_reach_light(s, p, wp, s.tmin) && !may_reach_light(s, p, wm, s.tmin))
+                    break;
                 Q.p[0] = p.x; Q.p[1] = p.y; Q.p[2] = p.z;
                 Q.wp[0] = wp.x; Q.wp[1] = wp.y; Q.wp[2] = wp.z;
                 Q.wm[0] = wm.x; Q.wm[1] = wm.y; Q.wm[2] = wm.z;

@@ -164,6 +164,33 @@ __device__ inline void radiance_pair(const SceneView& s, const Rng& rng, int bas
     Lm = radiance_hit(s, rng, base, o, dm, hm, camera, budget, stk, stride, wk);
 }
 
+// Whether the ray o + t d, t > tmin, may meet an emitter: a test against
+// every light triangle with margins (1e-4 in barycentric units, half of tmin)
+// far above the FP32 rounding of the traversal's own triangle test, so that
+// when it fails the traversal's closest hit is no emitter. A side path with
+// no bounce left then carries no radiance on that side. With more than
+// kLightScan light triangles it answers true.
+constexpr int kLightScan = 16;
+
+__device__ inline bool may_reach_light(const SceneView& s, v3 o, v3 d, float tmin) {
+    if (s.L > kLightScan) return true;
+    for (int i = 0; i < s.L; ++i) {
+        TriRec T = load_tri(s.tri, s.lights[i]);
+        v3 v0 = {T.a.x, T.a.y, T.a.z}, e1 = {T.a.w, T.b.x, T.b.y}, e2 = {T.b.z, T.b.w, T.c.x};
+        v3 pv = cross(d, e2);
+        float det = dot(e1, pv);
+        if (det == 0.0f) continue;
+        float inv = 1.0f / det;
+        v3 tv = o - v0;
+        float u = dot(tv, pv) * inv;
+        v3 qv = cross(tv, e1);
+        float v = dot(d, qv) * inv;
+        float t = dot(e2, qv) * inv;
+        if (u >= -1e-4f && v >= -1e-4f && u + v <= 1.0f + 1e-4f && t > 0.5f * tmin) return true;
+    }
+    return false;
+}
+
 // Geometry-buffer channel at the first hit x of triangle tri along d (Ch. 5,
 // Results: G-buffers): 1..3 position, 4..6 shading normal facing the ray,
 // 7 albedo; aov = 8 asks for all seven (aov_values).
