@@ -354,8 +354,8 @@ def main():
                     help="first run one plain device copy of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the gradient all-reduce across GPUs is a design note only)", file=sys.stderr)
+        print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the gradient all-reduce across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
