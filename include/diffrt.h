@@ -140,9 +140,10 @@ typedef struct {
      * leaves reached kept by weighted reservoir sampling with weight
      * n_e imp_e / pdf_e; the kept edge is weighted by W / (M imp) in place of
      * 1/pdf (W: total weight; unbiased because a leaf receives M pdf_e
-     * samples in expectation). M > 1 needs max_depth <= 3, no secondary
-     * proposal mixture and no geometry buffer, and is not taken by batches;
-     * otherwise, or M > 16: DR_ERROR_INVALID_VALUE. */
+     * samples in expectation). M > 1 needs max_depth <= 3, no proposal
+     * mixture (edge_pdf with edge_mix > 0, either term), no edge_stats and no
+     * geometry buffer, and is not taken by batches; otherwise, or M > 16:
+     * DR_ERROR_INVALID_VALUE. */
     int32_t  edge_candidates;
     /* Next event estimation for edges (drRenderBackward only; Ch. 5, Next
      * event estimation for edges). edge_nee = alpha in [0, 1) (0: off): each
@@ -159,10 +160,11 @@ typedef struct {
      * the scene's default, the L2 norm over the coordinates of 2% of the
      * mean absolute deviation of the vertex positions (computed at
      * drSceneCreate / drSceneUpdateVertices; drSceneRefit keeps it).
-     * alpha > 0 needs max_depth <= 3, edge_t_mode 0, edge_candidates <= 1,
-     * no secondary proposal mixture, no edge_stats and no geometry buffer,
-     * and is not taken by batches; otherwise, alpha outside [0, 1) or a
-     * negative or non-finite width: DR_ERROR_INVALID_VALUE. */
+     * alpha > 0 needs edge_t_mode 0, edge_candidates <= 1, no proposal
+     * mixture (edge_pdf with edge_mix > 0, either term), no edge_stats and
+     * no geometry buffer, and is not taken by batches; otherwise, alpha
+     * outside [0, 1) or a negative or non-finite width:
+     * DR_ERROR_INVALID_VALUE. */
     float    edge_nee;
     float    edge_nee_width;
 } drRenderOptions;

@@ -75,20 +75,21 @@ bool valid_camera(const drCamera* c) {
 }
 
 bool valid_options(const drRenderOptions* o) {
-    return o && o->spp >= 1 && o->max_depth >= 0 && o->max_depth <= kMaxDepth && (o->terms & ~DR_TERM_ALL) == 0 &&
-           o->edge_mix >= 0.0f && o->edge_mix < 1.0f &&
-           (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) == 0 && o->aov >= 0 && o->aov <= 8 &&
-           (o->aov == 0 || (o->edge_mix == 0.0f && !o->edge_stats)) && (o->edge_t_mode == 0 || o->edge_t_mode == 1) &&
-           o->edge_candidates >= 0 && o->edge_candidates <= kSelectMax &&
-           (o->edge_candidates <= 1 ||
-            (o->max_depth <= 3 && o->aov == 0 &&
-             !(o->edge_pdf && o->edge_mix > 0.0f &&
-               (o->edge_mix_terms == 0 || (o->edge_mix_terms & DR_TERM_SECONDARY))))) &&
-           o->edge_nee >= 0.0f && o->edge_nee < 1.0f && o->edge_nee_width >= 0.0f && std::isfinite(o->edge_nee_width) &&
-           (o->edge_nee == 0.0f ||
-            (o->max_depth <= 3 && o->aov == 0 && o->edge_t_mode == 0 && o->edge_candidates <= 1 && !o->edge_stats &&
-             !(o->edge_pdf && o->edge_mix > 0.0f &&
-               (o->edge_mix_terms == 0 || (o->edge_mix_terms & DR_TERM_SECONDARY)))));
+    if (!o || o->spp < 1 || o->max_depth < 0 || o->max_depth > kMaxDepth || (o->terms & ~DR_TERM_ALL) != 0) return false;
+    if (!(o->edge_mix >= 0.0f && o->edge_mix < 1.0f) ||
+        (o->edge_mix_terms & ~(uint32_t)(DR_TERM_PRIMARY | DR_TERM_SECONDARY)) != 0)
+        return false;
+    if (o->aov < 0 || o->aov > 8 || (o->aov != 0 && (o->edge_mix != 0.0f || o->edge_stats))) return false;
+    if (o->edge_t_mode != 0 && o->edge_t_mode != 1) return false;
+    if (o->edge_candidates < 0 || o->edge_candidates > kSelectMax) return false;
+    if (!(o->edge_nee >= 0.0f && o->edge_nee < 1.0f) || !(o->edge_nee_width >= 0.0f) || !std::isfinite(o->edge_nee_width))
+        return false;
+    // the multi-sample selection and the strip strategy run in their own
+    // sampling kernels, which the proposal-mixture / harvest kernels are not
+    bool mixture = (o->edge_pdf && o->edge_mix > 0.0f) || o->edge_stats;
+    if (o->edge_candidates > 1 && (o->max_depth > 3 || o->aov != 0 || mixture)) return false;
+    if (o->edge_nee > 0.0f && (o->aov != 0 || o->edge_t_mode != 0 || o->edge_candidates > 1 || mixture)) return false;
+    return true;
 }
 
 ViewKey make_key(const drScene_t* s, const drCamera& c, const drRenderOptions& o) {

@@ -1382,7 +1382,10 @@ __device__ inline int strip_mix_draw(const SceneView& s, const TreeView& tv, con
 // radiances of its queries and run the adjoint sweep.
 // AOV (with MAXD = 1, PH = 0): gradient of the geometry-buffer channel a.aov;
 // only the first hit, no NEE, no secondary term.
-template <int MAXD, int STK, bool CNT, bool MIX, int PH = 0, bool AOV = false>
+// NEE (with PH = 1): secondary edge samples from the strip strategy mixed with
+// the hierarchy (next event estimation for edges); its walks use the lane's
+// traversal stack, idle while an edge is drawn.
+template <int MAXD, int STK, bool CNT, bool MIX, int PH = 0, bool AOV = false, bool NEE = false>
 __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, const RenderArgs& a, const TreeView& tv,
                                               const float* __restrict__ d_image, float* __restrict__ dV,
                                               float* __restrict__ dA, float* __restrict__ camacc, const MixArgs& mx,
@@ -1499,11 +1502,16 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     bool dbg = m == a.debug_unit;
                     int ei;
                     int qi = -1;
+                    float te_draw = 0.0f;
                     if (PH == 2) {
                         qi = sp.qidx[(size_t)kk * a.M + m];
                         if (qi < 0) break;
                         ei = sp.q[qi].edge;
                         pdf = sp.q[qi].pdf;
+                    } else if (NEE) {
+                        TreeCtx q = tree_ctx(&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag);
+                        Rng rn{sid, a.view, kTagEnee + (uint32_t)(kk + 1), a.k0, a.k1};
+                        ei = strip_mix_draw(s, tv, q, a, rk, b0, rn, te_draw, pdf, my, BS, wk);
                     } else if (MIX && mx.sec) {
                         TreeCtx q = tree_ctx(&s, p, n, tv.cam, tri[kk], kHorizon * s.diag, kInsidePad * s.diag);
                         // proposal mixture: component from the third uniform of the
@@ -1530,7 +1538,7 @@ __device__ __forceinline__ void backward_body(const SceneView& s, const Cam& k, 
                     }
                     v3 pa = ld3(s.P, e.x), pb = ld3(s.P, e.y);
                     // the point on the edge: uniform in t, or by the clamped cosine
-                    float te = b0.y, pdf_t = 1.0f;
+                    float te = NEE ? te_draw : b0.y, pdf_t = 1.0f;
                     if (PH == 2) {
                         // the sampling pass's point (no transcendentals here)
                         te = sp.q[qi].te;
@@ -1739,11 +1747,12 @@ __global__ __launch_bounds__(BS) void k_backward(SceneView s, Cam k, RenderArgs 
 
 // Split backward, pass 1: secondary edge samples of every path vertex, their
 // side-path queries appended to a compact queue.
-template <int MAXD, int STK>
+template <int MAXD, int STK, bool NEE = false>
 __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp) {
     __shared__ int stk[STK * BS];
     MixArgs mx{};
-    backward_body<MAXD, STK, false, false, 1>(s, k, a, tv, nullptr, nullptr, nullptr, nullptr, mx, blockIdx.x * BS, stk, sp);
+    backward_body<MAXD, STK, false, false, 1, false, NEE>(s, k, a, tv, nullptr, nullptr, nullptr, nullptr, mx,
+                                                           blockIdx.x * BS, stk, sp);
 }
 
 // Split backward, pass 1, one lane per (path vertex, unit) when every vertex

@@ -24,6 +24,8 @@ void launch_paths_stack(const PathLaunch& p, hipStream_t st) {
             else if (p.a.nee > 0.0f)
                 k_bwd_sample_v<S, false, false, true><<<gv, b, 0, st>>>(p.sv, p.cam, p.a, p.tv, p.sp, nv, p.mx);
             else k_bwd_sample_v<S, false><<<gv, b, 0, st>>>(p.sv, p.cam, p.a, p.tv, p.sp, nv, p.mx);
+        } else if (p.a.nee > 0.0f) {
+            k_bwd_sample<D, S, true><<<g, b, 0, st>>>(p.sv, p.cam, p.a, p.tv, p.sp);
         } else {
             k_bwd_sample<D, S><<<g, b, 0, st>>>(p.sv, p.cam, p.a, p.tv, p.sp);
         }

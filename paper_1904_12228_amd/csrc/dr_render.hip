@@ -91,10 +91,12 @@ Variant v{o.aov != 0, use_mix, a.counters != nullptr, sm};
         dim3 g(nblk(a.M, BS));
         // the split kernels serve the mixture up to kernel depth 3, and the
         // multi-sample edge selection (which only they implement)
-        // the strip strategy of next event estimation for edges, likewise
+        // the strip strategy of next event estimation for edges, likewise, at
+        // any depth
         if (a.cands > 1 || a.nee > 0.0f) a.counters = nullptr;
         bool split = !a.counters && s->split_backward && (!use_mix || o.max_depth <= 3);
-        if ((a.cands > 1 || a.nee > 0.0f) && !(split && o.max_depth <= 3)) return DR_ERROR_INVALID_VALUE;
+        if (a.cands > 1 && !(split && o.max_depth <= 3)) return DR_ERROR_INVALID_VALUE;
+        if (a.nee > 0.0f && !split) return DR_ERROR_INVALID_VALUE;
         SplitArgs sp{};
         // queue capacity: MAXD (the kernels' template depth: 1, 3 or 6) slots per unit
         int maxd = o.max_depth <= 1 ? 1 : (o.max_depth <= 3 ? 3 : 6);

@@ -177,6 +177,14 @@ def test_edge_nee_sphere_box_depth3():
     _run(cfg.scene, cam, 2, 3, 2, nee=0.5)
 
 
+def test_edge_nee_sphere_box_depth5():
+    """Depth 5: vertices beyond the checkpoints are traced again by the
+    single sampling kernel, whose strip walks share the lane's traversal stack."""
+    cfg = sg.sphere_box(seed=1, level=2, width=48, height=48, spp=2, max_depth=5)
+    cam = cfg.camera.with_window(6, 8, 41, 37)
+    _run(cfg.scene, cam, 2, 5, 3, nee=0.5)
+
+
 def test_edge_nee_config3_window():
     cfg = sg.config3()
     cam = cfg.camera.with_window(300, 200, 331, 225)
@@ -205,10 +213,17 @@ def test_edge_nee_argument_checks():
     for kw in bad:
         with pytest.raises(RuntimeError):
             S.render_backward(cfg.camera, 1, 1, d, **kw)
-    with pytest.raises(RuntimeError):
-        S.render_backward(cfg.camera, 1, 4, d, edge_nee=0.5)
+    # not with a learned-proposal mixture of either term, nor the harvest
+    q = torch.full((S.num_edges,), 1.0 / S.num_edges, device="cuda")
+    st = torch.zeros(S.num_edges, device="cuda")
+    for kw in (dict(edge_pdf=q, edge_mix=0.5, edge_mix_terms=1), dict(edge_stats=st)):
+        with pytest.raises(RuntimeError):
+            S.render_backward(cfg.camera, 1, 1, d, edge_nee=0.5, **kw)
+        with pytest.raises(RuntimeError):
+            S.render_backward(cfg.camera, 1, 1, d, edge_candidates=4, **kw)
     S.render_backward(cfg.camera, 1, 1, d, edge_nee=0.5)
     S.render_backward(cfg.camera, 1, 3, d, edge_nee=0.3, edge_nee_width=0.05)
+    S.render_backward(cfg.camera, 1, 5, d, edge_nee=0.5)
     torch.cuda.synchronize()
     assert not S.device_error()
     S.close()
