@@ -165,11 +165,13 @@ __device__ inline void radiance_pair(const SceneView& s, const Rng& rng, int bas
 }
 
 // Whether the ray o + t d, t > tmin, may meet an emitter: a test against
-// every light triangle with margins (1e-4 in barycentric units, half of tmin)
-// far above the FP32 rounding of the traversal's own triangle test, so that
-// when it fails the traversal's closest hit is no emitter. A side path with
-// no bounce left then carries no radiance on that side. With more than
-// kLightScan light triangles it answers true.
+// every light triangle with margins far above the FP32 rounding of the
+// traversal's own triangle test (half of tmin in distance; 1e-4 in
+// barycentric units divided by the incidence cosine, since the rounding of
+// the barycentrics grows as the ray grazes the plane), so that when it fails
+// the traversal's closest hit is no emitter. A side path with no bounce left
+// then carries no radiance on that side. With more than kLightScan light
+// triangles it answers true.
 constexpr int kLightScan = 16;
 
 __device__ inline bool may_reach_light(const SceneView& s, v3 o, v3 d, float tmin) {
@@ -186,7 +188,8 @@ __device__ inline bool may_reach_light(const SceneView& s, v3 o, v3 d, float tmi
         v3 qv = cross(tv, e1);
         float v = dot(d, qv) * inv;
         float t = dot(e2, qv) * inv;
-        if (u >= -1e-4f && v >= -1e-4f && u + v <= 1.0f + 1e-4f && t > 0.5f * tmin) return true;
+        float eps = 1e-4f / fmaxf(fabsf(det) / (len(cross(e1, e2)) * len(d)), 1e-6f);
+        if (u >= -eps && v >= -eps && u + v <= 1.0f + eps && t > 0.5f * tmin) return true;
     }
     return false;
 }
