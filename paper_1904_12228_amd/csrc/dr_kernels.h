@@ -1762,15 +1762,15 @@ __global__ __launch_bounds__(BS) void k_bwd_sample(SceneView s, Cam k, RenderArg
 // Each lane rebuilds its unit's path up to its vertex with the adjoint pass's
 // arithmetic (same operations in the same order) and appends its side-path
 // query to segment kk of the queue.
-// No rays are traced here: no traversal stack (STK only names the variant).
-// SEL: the multi-sample edge selection, with sel_stk its LDS stack of
-// deferred children; NEE: the strip strategy (next event estimation for
-// edges) mixed with the hierarchy, with walk_stk the LDS stack of its walks
-// through the triangle BVH.
-template <int STK, bool MIX, bool SEL, bool NEE>
-__device__ __forceinline__ void bwd_sample_v_body(const SceneView& s, const Cam& k, const RenderArgs& a,
-                                                  const TreeView& tv, const SplitArgs& sp, int nvert, const MixArgs& mx,
-                                                  int* sel_stk, int* walk_stk) {
+template <int STK, bool MIX, bool SEL = false, bool NEE = false>
+__global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
+                                                     int nvert, MixArgs mx) {
+    // no rays are traced here: no traversal stack (STK only names the variant);
+    // SEL: the multi-sample edge selection and its LDS stack of deferred children;
+    // NEE: the strip strategy (next event estimation for edges) mixed with the
+    // hierarchy, and the LDS stack of its walks through the triangle BVH
+    __shared__ int sel_stk[SEL ? kSelectMax * 4 * BS : 1];
+    __shared__ int walk_stk[NEE ? STK * BS : 1];
     int lane = threadIdx.x;
     NoWork wk;
     long item = (long)blockIdx.x * BS + lane;
@@ -1902,21 +1902,6 @@ __device__ __forceinline__ void bwd_sample_v_body(const SceneView& s, const Cam&
         }
         left &= ~bal;
     }
-}
-
-template <int STK, bool MIX, bool SEL = false>
-__global__ __launch_bounds__(BS) void k_bwd_sample_v(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
-                                                     int nvert, MixArgs mx) {
-    __shared__ int sel_stk[SEL ? kSelectMax * 4 * BS : 1];
-    bwd_sample_v_body<STK, MIX, SEL, false>(s, k, a, tv, sp, nvert, mx, sel_stk, nullptr);
-}
-
-// The strip-strategy variant at five waves per SIMD (at most 96 VGPRs).
-template <int STK>
-__global__ __launch_bounds__(BS, 5) void k_bwd_sample_nee(SceneView s, Cam k, RenderArgs a, TreeView tv, SplitArgs sp,
-                                                          int nvert, MixArgs mx) {
-    __shared__ int walk_stk[STK * BS];
-    bwd_sample_v_body<STK, false, false, true>(s, k, a, tv, sp, nvert, mx, nullptr, walk_stk);
 }
 
 // Split backward, pass 2: both one-sided radiances of every queued query, one
